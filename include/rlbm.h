@@ -1,0 +1,226 @@
+/*
+ * rlbm.h -- C ABI of the MI355X (gfx950) relativistic lattice Boltzmann library.
+ *
+ * The method is the forced relativistic lattice Boltzmann model of
+ * M. Watson, "Two Dimensional Turbulence in a Massless Fluid with a
+ * Relativistic Lattice Boltzmann Model" (arXiv:2101.06187):
+ *   Sec. III A  relativistic Boltzmann equation with the Anderson-Witting
+ *               collision term, Juettner equilibrium, T^{mu nu}, Landau frame,
+ *               massless equation of state P = eps/3;
+ *   Sec. III B  angular-polynomial expansion (App. A), spherical off-lattice
+ *               momentum set streamed by linear interpolation;
+ *   Sec. III C  algorithm (a)-(f) and the projected stirring-force term (App. B);
+ *   Sec. IV     energy spectrum and vorticity;
+ *   Sec. V      2D periodic N x N x 1 lattice, spherical 26+1 momentum set,
+ *               random forcing on a band of the Fourier lattice.
+ *
+ * Units: lattice spacing 1, c = 1, time step dt = cfl, T0 = 1.  Populations
+ * F_q are the energy-weighted angular distribution, so T^{mu nu} =
+ * sum_q w_q F_q v_q^mu v_q^nu with v^0 = 1 (constant prefactor dropped).
+ *
+ * Conventions common to every call
+ *   - Every function returns an int status: RLBM_OK (0) or a negative code.
+ *     No C++ exception crosses this boundary.  rlbm_status_string() names a
+ *     code; rlbm_last_error() gives the text of the last failure on the
+ *     calling thread.
+ *   - Pointers named d_* are device pointers, h_* are host pointers.
+ *   - The caller owns all device memory (the workspace, field buffers, the
+ *     spectrum scratch) and the HIP stream.  The library never allocates or
+ *     frees device memory for user data; it allocates only its host-side
+ *     context, and graph-replay state inside the HIP runtime.
+ *   - Work is enqueued asynchronously on the stream given to *_init, except
+ *     calls that write h_* pointers (they synchronise that stream).
+ *   - Field arrays are FP64, row-major [ny][nx], x fastest, no padding.
+ *   - A context is used by one host thread at a time; contexts are independent.
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define RLBM_OK            0
+#define RLBM_EINVAL       -1  /* invalid argument (null pointer, size, range) */
+#define RLBM_ENOSPACE     -2  /* workspace / buffer too small */
+#define RLBM_EHIP         -3  /* a HIP runtime call failed (see rlbm_last_error) */
+#define RLBM_EUNSTABLE    -4  /* a site became unphysical: eps <= 0, |beta| >= 1,
+                                 non-finite, or the Landau solve did not converge */
+#define RLBM_EUNSUPPORTED -5  /* valid request this build does not support */
+
+/* ---- enumerations --------------------------------------------------------- */
+/* Momentum stencil.
+ * SPH26: the paper's spherical set (Sec. V: "D3Q27" made spherical, Sec. III B:
+ *   off-lattice, from the angular quadrature).  The 26 non-zero directions of
+ *   the 3x3x3 cube normalised to unit length, weights of the 26-point Lebedev
+ *   rule (faces 1/21, edges 4/105, corners 9/280; exact to degree 7).  The
+ *   zero momentum has weight 0 (a massless particle cannot be at rest) and is
+ *   not stored.  P = eps/3.
+ * CIRC8: 2+1-dimensional analogue, 8 in-plane directions at 2 pi q/8, weights
+ *   1/8, P = eps/2 (the 2D massless ideal gas).  Not the paper's stencil.    */
+enum { RLBM_STENCIL_SPH26 = 0, RLBM_STENCIL_CIRC8 = 1 };
+
+/* Population storage in HBM.  Arithmetic: FP64 for RLBM_F64, FP32 otherwise;
+ * the Landau-frame solve is FP64 in every form.  F16S/BF16S store F_q - 1
+ * (the rest equilibrium at eps = 1 is F_q = 1 for every q), rounded to nearest
+ * even.                                                                     */
+enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_F16S = 2, RLBM_BF16S = 3 };
+
+/* ---- parameter blocks ----------------------------------------------------- */
+typedef struct {
+    int32_t nx, ny;   /* lattice sites, 2 <= nx, ny <= 65536, periodic */
+    double  cfl;      /* c dt / dx in (0, 1]; a population moves cfl * v_q per step */
+} rlbm_lattice;
+
+/* Stirring force (Sec. III C / Sec. V).  Driven modes: integer (kx, ky) with
+ * k_lo <= |k| <= k_hi, half plane ky > 0 or (ky == 0, kx > 0), numbered in
+ * (ky, kx) lexicographic order; all strictly below Nyquist.  Each step s and
+ * mode m draws Philox4x32-10(counter = (m, s, realization, 0), key = seed)
+ * -> magnitude r, direction theta, phase phi, and
+ *   F(x, y) = amplitude * sum_m r_m (cos theta_m, sin theta_m)
+ *                              * cos(2 pi (kx x/nx + ky y/ny) + phi_m).
+ * amplitude == 0 means unforced.                                          */
+typedef struct {
+    double   amplitude;
+    double   k_lo, k_hi;
+    uint64_t seed;
+} rlbm_forcing;
+
+typedef struct rlbm_ctx rlbm_ctx;       /* one lattice; host-allocated by the library */
+typedef struct rlbm_batch rlbm_batch;   /* an ensemble of independent lattices        */
+
+/* ---- library info --------------------------------------------------------- */
+const char* rlbm_status_string(int status);
+const char* rlbm_last_error(void);
+
+/* Direction table of a stencil in the library's storage order.
+ * *h_q receives Q (26 or 8); h_v (3*Q doubles, may be NULL) the unit vectors
+ * (vx, vy, vz) per direction; h_w (Q doubles, may be NULL) the weights.
+ * Pure host function.                                                      */
+int rlbm_stencil_info(int stencil, int32_t* h_q, double* h_v, double* h_w);
+
+/* Driven forcing modes for a lattice (host logic only, no device work).
+ * Writes up to cap (kx, ky) pairs into h_kx/h_ky (either may be NULL when cap
+ * is 0) and the total count into *h_n.  EINVAL if the shell reaches Nyquist.   */
+int rlbm_forcing_modes(const rlbm_lattice* lat, const rlbm_forcing* forcing,
+                       int32_t* h_kx, int32_t* h_ky, int32_t cap, int32_t* h_n);
+
+/* ---- one lattice ------------------------------------------------------------ */
+
+/* Bytes of device workspace rlbm_init needs (two population buffers of
+ * Q * ny * pitch elements plus forcing tables and a few KB of control data).
+ * forcing may be NULL (unforced).                                          */
+int rlbm_workspace_bytes(const rlbm_lattice* lat, int stencil, int storage,
+                         const rlbm_forcing* forcing, size_t* h_bytes);
+
+/* Create a context on caller memory.  tau = tau_R / dt (> 0.5), the
+ * relaxation time of the Anderson-Witting term (Sec. III A).  d_workspace
+ * must stay valid until rlbm_destroy; hip_stream (hipStream_t, may be NULL
+ * for the null stream) is where all work is enqueued.  The populations are
+ * undefined until rlbm_set_state / rlbm_set_populations / rlbm_load.
+ * Errors: EINVAL (bad lattice, tau <= 0.5, cfl outside (0, 1], k_lo > k_hi,
+ * shell at or above Nyquist, unknown enum, null pointer), ENOSPACE, EHIP.  */
+int rlbm_init(rlbm_ctx** out, const rlbm_lattice* lat, double tau, int stencil,
+              const rlbm_forcing* forcing, int storage,
+              void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Step (a) of Sec. III C: F_q := F_eq,q(eps, beta) at every site (the
+ * truncated Juettner equilibrium of Sec. III B), step counter := 0, stability
+ * flag cleared.  d_e, d_ux, d_uy: FP64 [ny][nx] device arrays of the Landau
+ * energy density and the 3-velocity beta (u^mu = gamma (1, beta)).        */
+int rlbm_set_state(rlbm_ctx* ctx, const double* d_e, const double* d_ux,
+                   const double* d_uy);
+
+/* Advance n >= 0 time steps, each: stream (linear interpolation, periodic),
+ * moments, FP64 Landau frame, equilibrium, Anderson-Witting collision, force
+ * term, store (Sec. III C (b)-(e)).  Asynchronous; never synchronises.  The
+ * stability flag is only read by rlbm_check.                               */
+int rlbm_step(rlbm_ctx* ctx, int64_t n);
+
+/* Synchronise the stream and return RLBM_EUNSTABLE if any site of any step
+ * since the last set_state/load became unphysical, else RLBM_OK.           */
+int rlbm_check(rlbm_ctx* ctx);
+
+/* Steps taken since the last set_state (restored by rlbm_load).           */
+int rlbm_step_count(const rlbm_ctx* ctx, int64_t* h_steps);
+
+/* Macroscopic fields at the current time: stage (c) of Sec. III C applied to
+ * the current populations -- stream them, form T^{mu nu}, solve the Landau
+ * frame in FP64 (the moments the next step computes).  Any output pointer may
+ * be NULL.  d_e, d_ux, d_uy: [ny][nx]; d_T: 6 planes [6][ny][nx] holding
+ * T^00, T^0x, T^0y, T^xx, T^xy, T^yy.                                     */
+int rlbm_fields(rlbm_ctx* ctx, double* d_e, double* d_ux, double* d_uy,
+                double* d_T);
+
+/* Sum over the lattice of T^00, T^0x, T^0y of the stored populations, FP64,
+ * deterministic order.  Synchronises.                                      */
+int rlbm_conserved(rlbm_ctx* ctx, double h_out[3]);
+
+/* Populations as FP64 planes [Q][ny][nx] in the order of rlbm_stencil_info
+ * (converted from / to the storage type).  For tests and tooling.          */
+int rlbm_get_populations(rlbm_ctx* ctx, double* d_out);
+int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in);
+
+/* Energy spectrum and enstrophy of the current fields (Sec. IV):
+ *   E(k_b) = sum over integer k with round(|k|) = k_b of 1/2 |beta_hat(k)|^2,
+ *   beta_hat = DFT(beta)/(nx ny), k in [-n/2, n/2)^2, b = 0 .. nbins-1;
+ *   Z = 1/2 sum_k |i (2 pi kx/nx) beta_hat_y - i (2 pi ky/ny) beta_hat_x|^2.
+ * nx and ny must be powers of two (EUNSUPPORTED otherwise).  d_scratch must
+ * hold rlbm_spectrum_scratch_bytes() bytes.  h_Ek: nbins doubles;
+ * h_enstrophy may be NULL.  Synchronises.                                  */
+int rlbm_spectrum_scratch_bytes(const rlbm_ctx* ctx, size_t* h_bytes);
+int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
+                  double* h_Ek, int32_t nbins, double* h_enstrophy);
+
+/* Checkpoint: a self-describing host blob (header: lattice, stencil,
+ * storage, tau, forcing, step counter; then the populations in the storage
+ * type).  A run resumed from it continues bit for bit, because the forcing
+ * is counter-based.  rlbm_load rejects a blob of another configuration
+ * (EINVAL).  Both synchronise.                                             */
+int rlbm_state_bytes(const rlbm_ctx* ctx, size_t* h_bytes);
+int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes);
+int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
+
+/* Launch shape: tile height th in {1, 2, 4, 8} rows of 64 sites per block.
+ * Results do not depend on it (bitwise).  rlbm_autotune times every tile
+ * height for `steps` steps (advancing the state) and keeps the fastest;
+ * *h_th receives it.                                                       */
+int rlbm_set_tile(rlbm_ctx* ctx, int32_t th);
+int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th);
+
+/* Replay rlbm_step in chunks of `chunk` steps through a captured HIP graph
+ * (0 = direct launches).  Results are identical either way.               */
+int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk);
+
+void rlbm_destroy(rlbm_ctx* ctx);
+
+/* ---- ensemble of independent lattices --------------------------------------- */
+/* n_real realizations, each with its own lattice, tau and forcing
+ * (forcings may be NULL: all unforced); realization r draws its forcing with
+ * Philox counter word 2 = r.  All share the stencil and the storage.  One
+ * persistent kernel advances every lattice per step.                       */
+int rlbm_batch_workspace_bytes(int32_t n_real, const rlbm_lattice* lats,
+                               int stencil, int storage,
+                               const rlbm_forcing* forcings, size_t* h_bytes);
+int rlbm_batch_init(rlbm_batch** out, int32_t n_real, const rlbm_lattice* lats,
+                    const double* taus, int stencil,
+                    const rlbm_forcing* forcings, int storage,
+                    void* d_workspace, size_t ws_bytes, void* hip_stream);
+int rlbm_batch_set_state(rlbm_batch* b, int32_t r, const double* d_e,
+                         const double* d_ux, const double* d_uy);
+int rlbm_batch_step(rlbm_batch* b, int64_t n);
+int rlbm_batch_check(rlbm_batch* b);
+int rlbm_batch_fields(rlbm_batch* b, int32_t r, double* d_e, double* d_ux,
+                      double* d_uy, double* d_T);
+int rlbm_batch_get_populations(rlbm_batch* b, int32_t r, double* d_out);
+int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk);
+void rlbm_batch_destroy(rlbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLBM_H */

@@ -71,3 +71,21 @@ def force_field(nx, ny, amplitude, k_lo, k_hi, seed, step, realization=0):
         fx += amplitude * rm * np.cos(th) * c
         fy += amplitude * rm * np.sin(th) * c
     return fx, fy
+
+
+def force_at(nx, ny, amplitude, k_lo, k_hi, seed, step, xs, ys, realization=0):
+    """The same force evaluated only at the points (xs, ys), by direct summation
+    (for sampled checks on lattices too large for ``force_field``)."""
+    xs = np.asarray(xs, dtype=np.float64)
+    ys = np.asarray(ys, dtype=np.float64)
+    fx = np.zeros(xs.shape)
+    fy = np.zeros(xs.shape)
+    km = modes(nx, ny, k_lo, k_hi)
+    if amplitude == 0.0 or len(km) == 0:
+        return fx, fy
+    r, theta, phi = mode_draws(len(km), seed, step, realization)
+    for (kx, ky), rm, th, ph in zip(km, r, theta, phi):
+        c = np.cos(2.0 * np.pi * (kx * xs / nx + ky * ys / ny) + ph)
+        fx += amplitude * rm * np.cos(th) * c
+        fy += amplitude * rm * np.sin(th) * c
+    return fx, fy

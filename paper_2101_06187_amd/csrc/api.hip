@@ -1,0 +1,871 @@
+// C ABI of the RLBM library: argument validation, workspace layout, forcing
+// mode tables, launch sequencing (direct or through a captured HIP graph),
+// diagnostics and checkpoints.  All device memory belongs to the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+
+using namespace rlbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return fail(RLBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int storage_bytes(int storage) {
+    return storage == RLBM_F64 ? 8 : (storage == RLBM_F32 ? 4 : 2);
+}
+int stencil_q(int stencil) { return stencil == RLBM_STENCIL_SPH26 ? 26 : 8; }
+int stencil_d(int stencil) { return stencil == RLBM_STENCIL_SPH26 ? 3 : 2; }
+
+struct ModeTable {
+    std::vector<int4> modes;    // grouped by |kx|: (kx, ky, m, 0)
+    std::vector<int> kptr;      // K + 2 entries
+    int K = -1;
+    int n = 0;
+};
+
+// Driven modes (Sec. V): integer (kx, ky), k_lo <= |k| <= k_hi, half plane
+// ky > 0 or (ky == 0 and kx > 0), numbered in (ky, kx) lexicographic order.
+int build_modes(const rlbm_lattice& lat, const rlbm_forcing* f, ModeTable& mt) {
+    mt = ModeTable{};
+    if (!f || f->amplitude == 0.0) return RLBM_OK;
+    if (!(f->k_lo >= 0.0) || !(f->k_hi >= f->k_lo) || !std::isfinite(f->k_hi) ||
+        !std::isfinite(f->amplitude))
+        return fail(RLBM_EINVAL, "forcing shell must satisfy 0 <= k_lo <= k_hi, finite amplitude");
+    const int kmax = (int)std::floor(f->k_hi) + 1;
+    const double lo2 = f->k_lo * f->k_lo, hi2 = f->k_hi * f->k_hi;
+    std::vector<int4> lex;
+    for (int ky = 0; ky <= kmax; ++ky)
+        for (int kx = -kmax; kx <= kmax; ++kx) {
+            if (ky == 0 && kx <= 0) continue;
+            const double k2 = (double)kx * kx + (double)ky * ky;
+            if (k2 < lo2 || k2 > hi2) continue;
+            if (2 * std::abs(kx) >= lat.nx || 2 * ky >= lat.ny)
+                return fail(RLBM_EINVAL, "forcing shell reaches the Nyquist wave number");
+            lex.push_back(make_int4(kx, ky, (int)lex.size(), 0));
+        }
+    mt.n = (int)lex.size();
+    if (mt.n == 0) return RLBM_OK;
+    for (const int4& m : lex) mt.K = std::max(mt.K, std::abs(m.x));
+    mt.kptr.assign(mt.K + 2, 0);
+    for (int k = 0; k <= mt.K; ++k) {
+        mt.kptr[k] = (int)mt.modes.size();
+        for (const int4& m : lex)
+            if (std::abs(m.x) == k) mt.modes.push_back(m);
+    }
+    mt.kptr[mt.K + 1] = (int)mt.modes.size();
+    return RLBM_OK;
+}
+
+int validate_lattice(const rlbm_lattice* lat) {
+    if (!lat) return fail(RLBM_EINVAL, "lattice is NULL");
+    if (lat->nx < 2 || lat->ny < 2 || lat->nx > 65536 || lat->ny > 65536)
+        return fail(RLBM_EINVAL, "lattice sides must be in [2, 65536]");
+    if (!(lat->cfl > 0.0 && lat->cfl <= 1.0)) return fail(RLBM_EINVAL, "cfl must be in (0, 1]");
+    return RLBM_OK;
+}
+
+int pitch_of(int nx) { return (nx + kTileW - 1) / kTileW * kTileW; }
+
+// Workspace layout of one engine (descriptors, control words, reduction
+// partials, tile map, then per lattice: two population buffers, twiddles,
+// force tables, mode tables).
+struct Layout {
+    size_t ctl = 0, desc = 0, red = 0, tiles = 0, total = 0;
+    struct Per { size_t buf0, buf1, tw64, tw32, g64, g32, modes, kptr; };
+    std::vector<Per> per;
+    int max_partials = 0;
+};
+
+int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storage,
+                   const std::vector<ModeTable>& mts, Layout& L) {
+    const int Q = stencil_q(stencil), s = storage_bytes(storage);
+    size_t off = 0;
+    L.ctl = off; off = align_up(off + 64);
+    L.desc = off; off = align_up(off + sizeof(RealDesc) * (size_t)n_real);
+    int maxp = 1;
+    long long tiles1 = 0;
+    for (int r = 0; r < n_real; ++r) {
+        maxp = std::max(maxp, conserved_partials(lats[r].nx, lats[r].ny));
+        tiles1 += (long long)((lats[r].nx + kTileW - 1) / kTileW) * lats[r].ny;
+    }
+    L.max_partials = maxp;
+    L.red = off; off = align_up(off + sizeof(double) * (3 * (size_t)maxp + 8));
+    L.tiles = off;
+    if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)tiles1);
+    L.per.resize(n_real);
+    for (int r = 0; r < n_real; ++r) {
+        const size_t plane = (size_t)pitch_of(lats[r].nx) * lats[r].ny;
+        auto& P = L.per[r];
+        P.buf0 = off; off = align_up(off + plane * Q * s);
+        P.buf1 = off; off = align_up(off + plane * Q * s);
+        P.tw64 = off; off = align_up(off + sizeof(double) * 2 * lats[r].nx);
+        P.tw32 = off; off = align_up(off + sizeof(float) * 2 * lats[r].nx);
+        const size_t g = (size_t)lats[r].ny * (mts[r].K + 1) * 4;
+        P.g64 = off; off = align_up(off + sizeof(double) * g);
+        P.g32 = off; off = align_up(off + sizeof(float) * g);
+        P.modes = off; off = align_up(off + sizeof(int4) * mts[r].modes.size());
+        P.kptr = off; off = align_up(off + sizeof(int) * mts[r].kptr.size());
+    }
+    L.total = off;
+    return RLBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// engine: one or more independent lattices advanced by one launch per step
+// ---------------------------------------------------------------------------
+struct Engine {
+    int n_real = 0, stencil = 0, storage = 0, Q = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout lay;
+    std::vector<rlbm_lattice> lats;
+    std::vector<double> taus;
+    std::vector<rlbm_forcing> frc;
+    std::vector<ModeTable> mts;
+    std::vector<RealDesc> hdesc;
+    RealDesc* d_desc = nullptr;
+    int64_t* d_step = nullptr;
+    int* d_flag = nullptr;
+    double* d_red = nullptr;
+    uint16_t* d_tiles = nullptr;
+    bool unit_cfl = true, any_forced = false;
+    int max_rows = 0, max_k = -1;
+    int th = 4, n_tiles = 0, grid = 0, cus = 0;
+    int64_t step = 0;
+    int graph_chunk = 0;
+    int graph_built_chunk = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+
+    ~Engine() { drop_graph(); if (cap_stream) (void)hipStreamDestroy(cap_stream); }
+
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        graph_built_chunk = 0;
+    }
+
+    int occupancy() const {
+        switch (storage) {
+            case RLBM_F64: return occ_f64(stencil, unit_cfl, any_forced, th);
+            case RLBM_F32: return occ_f32(stencil, unit_cfl, any_forced, th);
+            case RLBM_F16S: return occ_f16s(stencil, unit_cfl, any_forced, th);
+            default: return occ_bf16s(stencil, unit_cfl, any_forced, th);
+        }
+    }
+
+    // tiles of height th, tile map, persistent grid
+    int configure_tiles() {
+        n_tiles = 0;
+        std::vector<uint16_t> map;
+        for (int r = 0; r < n_real; ++r) {
+            RealDesc& d = hdesc[r];
+            d.tiles_x = (d.nx + kTileW - 1) / kTileW;
+            d.tiles_y = (d.ny + th - 1) / th;
+            d.tile_begin = n_tiles;
+            n_tiles += d.tiles_x * d.tiles_y;
+            if (n_real > 1) map.insert(map.end(), (size_t)d.tiles_x * d.tiles_y, (uint16_t)r);
+        }
+        HIPCHK(hipMemcpyAsync(d_desc, hdesc.data(), sizeof(RealDesc) * n_real,
+                              hipMemcpyHostToDevice, stream));
+        if (n_real > 1)
+            HIPCHK(hipMemcpyAsync(d_tiles, map.data(), sizeof(uint16_t) * map.size(),
+                                  hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        const int per_cu = occupancy();
+        grid = std::max(8, std::min(n_tiles, cus * per_cu));
+        drop_graph();
+        return RLBM_OK;
+    }
+
+    hipError_t launch_one(int step_off) {
+        StepLaunch L;
+        L.args.desc = d_desc;
+        L.args.tile_real = n_real > 1 ? d_tiles : nullptr;
+        L.args.d_step = d_step;
+        L.args.d_flag = d_flag;
+        L.args.step_off = step_off;
+        L.args.n_tiles = n_tiles;
+        L.args.th = th;
+        L.stencil = stencil;
+        L.unit_cfl = unit_cfl;
+        L.forced = any_forced;
+        L.grid = grid;
+        L.stream = stream;
+        return launch_on(L);
+    }
+
+    hipError_t launch_on(StepLaunch& L) {
+        if (any_forced) {
+            hipError_t e = launch_force_table(d_desc, n_real, max_rows, max_k, d_step,
+                                              L.args.step_off, storage != RLBM_F64, L.stream);
+            if (e != hipSuccess) return e;
+        }
+        switch (storage) {
+            case RLBM_F64: return launch_step_f64(L);
+            case RLBM_F32: return launch_step_f32(L);
+            case RLBM_F16S: return launch_step_f16s(L);
+            default: return launch_step_bf16s(L);
+        }
+    }
+
+    int build_graph(int chunk) {
+        drop_graph();
+        if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (int i = 0; i < chunk && err == hipSuccess; ++i) {
+            StepLaunch L;
+            L.args.desc = d_desc;
+            L.args.tile_real = n_real > 1 ? d_tiles : nullptr;
+            L.args.d_step = d_step;
+            L.args.d_flag = d_flag;
+            L.args.step_off = i;
+            L.args.n_tiles = n_tiles;
+            L.args.th = th;
+            L.stencil = stencil;
+            L.unit_cfl = unit_cfl;
+            L.forced = any_forced;
+            L.grid = grid;
+            L.stream = cap_stream;
+            err = launch_on(L);
+        }
+        if (err == hipSuccess) err = launch_advance(d_step, chunk, cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(RLBM_EHIP, std::string("graph capture failed: ") +
+                                       hipGetErrorString(err != hipSuccess ? err : e2));
+        }
+        graph = g;
+        HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        graph_built_chunk = chunk;
+        return RLBM_OK;
+    }
+
+    int run(int64_t n) {
+        if (n < 0) return fail(RLBM_EINVAL, "negative step count");
+        int64_t done = 0;
+        if (graph_chunk > 0 && n >= graph_chunk) {
+            if (graph_built_chunk != graph_chunk) {
+                int rc = build_graph(graph_chunk);
+                if (rc != RLBM_OK) return rc;
+            }
+            while (n - done >= graph_chunk) {
+                HIPCHK(hipGraphLaunch(gexec, stream));
+                done += graph_chunk;
+            }
+        }
+        const int64_t rest = n - done;
+        for (int64_t i = 0; i < rest; ++i) HIPCHK(launch_one((int)i));
+        if (rest > 0) HIPCHK(launch_advance(d_step, rest, stream));
+        step += n;
+        return RLBM_OK;
+    }
+
+    int parity() const { return (int)(step & 1); }
+};
+
+struct rlbm_ctx { Engine e; };
+struct rlbm_batch { Engine e; };
+
+namespace {
+
+int engine_bytes(int n_real, const rlbm_lattice* lats, int stencil, int storage,
+                 const rlbm_forcing* forcings, size_t* out) {
+    if (!lats || !out) return fail(RLBM_EINVAL, "NULL argument");
+    if (n_real < 1 || n_real > 65535) return fail(RLBM_EINVAL, "n_real must be in [1, 65535]");
+    if (stencil != RLBM_STENCIL_SPH26 && stencil != RLBM_STENCIL_CIRC8)
+        return fail(RLBM_EINVAL, "unknown stencil");
+    if (storage < RLBM_F64 || storage > RLBM_BF16S) return fail(RLBM_EINVAL, "unknown storage");
+    std::vector<ModeTable> mts(n_real);
+    for (int r = 0; r < n_real; ++r) {
+        int rc = validate_lattice(&lats[r]);
+        if (rc) return rc;
+        const long long plane = (long long)pitch_of(lats[r].nx) * lats[r].ny;
+        if (plane * (long long)storage_bytes(storage) >= (1LL << 31))
+            return fail(RLBM_EINVAL, "one population plane must stay below 2 GiB");
+        rc = build_modes(lats[r], forcings ? &forcings[r] : nullptr, mts[r]);
+        if (rc) return rc;
+    }
+    Layout L;
+    compute_layout(n_real, lats, stencil, storage, mts, L);
+    *out = L.total;
+    return RLBM_OK;
+}
+
+int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* taus, int stencil,
+                const rlbm_forcing* forcings, int storage, void* ws, size_t ws_bytes,
+                void* stream) {
+    size_t need = 0;
+    int rc = engine_bytes(n_real, lats, stencil, storage, forcings, &need);
+    if (rc) return rc;
+    if (!taus) return fail(RLBM_EINVAL, "tau is NULL");
+    for (int r = 0; r < n_real; ++r)
+        if (!(taus[r] > 0.5) || !std::isfinite(taus[r]))
+            return fail(RLBM_EINVAL, "tau must be finite and > 0.5");
+    if (!ws) return fail(RLBM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)ws % kAlign) return fail(RLBM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(RLBM_ENOSPACE, "workspace too small");
+
+    E.n_real = n_real;
+    E.stencil = stencil;
+    E.storage = storage;
+    E.Q = stencil_q(stencil);
+    E.stream = (hipStream_t)stream;
+    E.ws = (char*)ws;
+    E.lats.assign(lats, lats + n_real);
+    E.taus.assign(taus, taus + n_real);
+    E.frc.assign(n_real, rlbm_forcing{0.0, 0.0, 0.0, 0});
+    if (forcings) E.frc.assign(forcings, forcings + n_real);
+    E.mts.resize(n_real);
+    for (int r = 0; r < n_real; ++r) build_modes(lats[r], &E.frc[r], E.mts[r]);
+    compute_layout(n_real, lats, stencil, storage, E.mts, E.lay);
+
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&E.cus, hipDeviceAttributeMultiprocessorCount, dev));
+
+    E.d_step = (int64_t*)(E.ws + E.lay.ctl);
+    E.d_flag = (int*)(E.ws + E.lay.ctl + 8);
+    E.d_desc = (RealDesc*)(E.ws + E.lay.desc);
+    E.d_red = (double*)(E.ws + E.lay.red);
+    E.d_tiles = (uint16_t*)(E.ws + E.lay.tiles);
+    E.hdesc.assign(n_real, RealDesc{});
+    E.unit_cfl = true;
+    E.any_forced = false;
+    E.max_rows = 0;
+    E.max_k = -1;
+    const int s = storage_bytes(storage);
+    for (int r = 0; r < n_real; ++r) {
+        const auto& P = E.lay.per[r];
+        const auto& lat = lats[r];
+        RealDesc& d = E.hdesc[r];
+        std::memset(&d, 0, sizeof(d));
+        d.buf[0] = E.ws + P.buf0;
+        d.buf[1] = E.ws + P.buf1;
+        d.tw64 = (const double*)(E.ws + P.tw64);
+        d.tw32 = (const float*)(E.ws + P.tw32);
+        d.g64 = (double*)(E.ws + P.g64);
+        d.g32 = (float*)(E.ws + P.g32);
+        d.modes = (const int4*)(E.ws + P.modes);
+        d.kptr = (const int*)(E.ws + P.kptr);
+        d.nx = lat.nx;
+        d.ny = lat.ny;
+        d.pitch = pitch_of(lat.nx);
+        d.plane = (long long)d.pitch * lat.ny;
+        d.K = E.mts[r].n > 0 ? E.mts[r].K : -1;
+        d.n_modes = E.mts[r].n;
+        d.realization = r;
+        d.seed = E.frc[r].seed;
+        d.amplitude = E.frc[r].amplitude;
+        d.inv_tau = 1.0 / taus[r];
+        d.a[0] = lat.cfl;
+        d.a[1] = lat.cfl * kInvSqrt2;
+        d.a[2] = lat.cfl * kInvSqrt3;
+        d.dt = lat.cfl;
+        for (int i = 0; i < 3; ++i) d.af[i] = (float)d.a[i];
+        d.dtf = (float)d.dt;
+        d.inv_tauf = (float)d.inv_tau;
+        if (lat.cfl != 1.0) E.unit_cfl = false;
+        if (d.K >= 0) {
+            E.any_forced = true;
+            E.max_rows = std::max(E.max_rows, lat.ny);
+            E.max_k = std::max(E.max_k, d.K);
+        }
+        (void)s;
+    }
+    // twiddles and mode tables (host -> workspace, synchronous at init)
+    for (int r = 0; r < n_real; ++r) {
+        const auto& P = E.lay.per[r];
+        const int nx = lats[r].nx;
+        std::vector<double> t64(2 * nx);
+        std::vector<float> t32(2 * nx);
+        for (int x = 0; x < nx; ++x) {
+            const double a = 2.0 * M_PI * (double)x / (double)nx;
+            t64[2 * x] = std::cos(a);
+            t64[2 * x + 1] = std::sin(a);
+            t32[2 * x] = (float)t64[2 * x];
+            t32[2 * x + 1] = (float)t64[2 * x + 1];
+        }
+        HIPCHK(hipMemcpyAsync(E.ws + P.tw64, t64.data(), sizeof(double) * t64.size(),
+                              hipMemcpyHostToDevice, E.stream));
+        HIPCHK(hipMemcpyAsync(E.ws + P.tw32, t32.data(), sizeof(float) * t32.size(),
+                              hipMemcpyHostToDevice, E.stream));
+        if (!E.mts[r].modes.empty()) {
+            HIPCHK(hipMemcpyAsync(E.ws + P.modes, E.mts[r].modes.data(),
+                                  sizeof(int4) * E.mts[r].modes.size(), hipMemcpyHostToDevice,
+                                  E.stream));
+            HIPCHK(hipMemcpyAsync(E.ws + P.kptr, E.mts[r].kptr.data(),
+                                  sizeof(int) * E.mts[r].kptr.size(), hipMemcpyHostToDevice,
+                                  E.stream));
+        }
+        HIPCHK(hipStreamSynchronize(E.stream));
+    }
+    HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
+    E.step = 0;
+    return E.configure_tiles();
+}
+
+int check_ctx(const void* p) { return p ? RLBM_OK : fail(RLBM_EINVAL, "context is NULL"); }
+
+int engine_set_state(Engine& E, int r, const double* d_e, const double* d_ux,
+                     const double* d_uy, bool reset_step) {
+    if (!d_e || !d_ux || !d_uy) return fail(RLBM_EINVAL, "NULL field pointer");
+    if (reset_step) {
+        HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
+        E.step = 0;
+    }
+    HIPCHK(launch_set_state(E.d_desc, r, E.storage, E.stencil, E.lats[r].nx, E.lats[r].ny, d_e,
+                            d_ux, d_uy, E.parity(), E.stream));
+    return RLBM_OK;
+}
+
+int engine_fields(Engine& E, int r, double* d_e, double* d_ux, double* d_uy, double* d_T,
+                  double2* z) {
+    HIPCHK(launch_fields(E.d_desc, r, E.storage, E.stencil, E.lats[r].cfl == 1.0, E.lats[r].nx,
+                         E.lats[r].ny, E.parity(), d_e, d_ux, d_uy, d_T, z, E.d_flag, E.stream));
+    return RLBM_OK;
+}
+
+int engine_check(Engine& E) {
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, E.d_flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    return flag ? fail(RLBM_EUNSTABLE, "a site became unphysical") : RLBM_OK;
+}
+
+// checkpoint header
+struct SaveHeader {
+    char magic[8];
+    int32_t version, stencil, storage, nx, ny, Q;
+    int64_t step;
+    double tau, cfl, amplitude, k_lo, k_hi;
+    uint64_t seed;
+};
+
+}  // namespace
+
+// ===========================================================================
+// exported C ABI
+// ===========================================================================
+extern "C" {
+
+const char* rlbm_status_string(int status) {
+    switch (status) {
+        case RLBM_OK: return "ok";
+        case RLBM_EINVAL: return "invalid argument";
+        case RLBM_ENOSPACE: return "workspace or buffer too small";
+        case RLBM_EHIP: return "HIP runtime error";
+        case RLBM_EUNSTABLE: return "unstable: a site became unphysical";
+        case RLBM_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* rlbm_last_error(void) { return g_err.c_str(); }
+
+int rlbm_stencil_info(int stencil, int32_t* h_q, double* h_v, double* h_w) {
+    if (!h_q) return fail(RLBM_EINVAL, "h_q is NULL");
+    auto fill = [&](auto st) {
+        using St = decltype(st);
+        *h_q = St::Q;
+        for (int q = 0; q < St::Q; ++q) {
+            for (int a = 0; a < 3; ++a)
+                if (h_v) h_v[3 * q + a] = dir_comp(St::dir[q], a);
+            if (h_w) {
+                for (int c = 0; c < St::NC; ++c)
+                    if (q >= St::cls[c].first &&
+                        q < St::cls[c].first + St::cls[c].nplus + St::cls[c].nminus)
+                        h_w[q] = St::cls[c].w;
+            }
+        }
+    };
+    if (stencil == RLBM_STENCIL_SPH26) fill(Sph26{});
+    else if (stencil == RLBM_STENCIL_CIRC8) fill(Circ8{});
+    else return fail(RLBM_EINVAL, "unknown stencil");
+    return RLBM_OK;
+}
+
+int rlbm_forcing_modes(const rlbm_lattice* lat, const rlbm_forcing* forcing, int32_t* h_kx,
+                       int32_t* h_ky, int32_t cap, int32_t* h_n) {
+    int rc = validate_lattice(lat);
+    if (rc) return rc;
+    if (!h_n || cap < 0 || (cap > 0 && (!h_kx || !h_ky))) return fail(RLBM_EINVAL, "bad output");
+    ModeTable mt;
+    rc = build_modes(*lat, forcing, mt);
+    if (rc) return rc;
+    // back to lexicographic order
+    std::vector<int4> lex(mt.modes);
+    std::sort(lex.begin(), lex.end(), [](const int4& a, const int4& b) { return a.z < b.z; });
+    for (int i = 0; i < (int)lex.size() && i < cap; ++i) {
+        h_kx[i] = lex[i].x;
+        h_ky[i] = lex[i].y;
+    }
+    *h_n = mt.n;
+    return RLBM_OK;
+}
+
+int rlbm_workspace_bytes(const rlbm_lattice* lat, int stencil, int storage,
+                         const rlbm_forcing* forcing, size_t* h_bytes) {
+    return engine_bytes(1, lat, stencil, storage, forcing, h_bytes);
+}
+
+int rlbm_init(rlbm_ctx** out, const rlbm_lattice* lat, double tau, int stencil,
+              const rlbm_forcing* forcing, int storage, void* d_workspace, size_t ws_bytes,
+              void* hip_stream) {
+    if (!out) return fail(RLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    rlbm_ctx* c = new (std::nothrow) rlbm_ctx();
+    if (!c) return fail(RLBM_EINVAL, "out of host memory");
+    int rc = engine_init(c->e, 1, lat, &tau, stencil, forcing, storage, d_workspace, ws_bytes,
+                         hip_stream);
+    if (rc) { delete c; return rc; }
+    *out = c;
+    return RLBM_OK;
+}
+
+int rlbm_set_state(rlbm_ctx* ctx, const double* d_e, const double* d_ux, const double* d_uy) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return engine_set_state(ctx->e, 0, d_e, d_ux, d_uy, true);
+}
+
+int rlbm_step(rlbm_ctx* ctx, int64_t n) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return ctx->e.run(n);
+}
+
+int rlbm_check(rlbm_ctx* ctx) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return engine_check(ctx->e);
+}
+
+int rlbm_step_count(const rlbm_ctx* ctx, int64_t* h_steps) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!h_steps) return fail(RLBM_EINVAL, "NULL output");
+    *h_steps = ctx->e.step;
+    return RLBM_OK;
+}
+
+int rlbm_fields(rlbm_ctx* ctx, double* d_e, double* d_ux, double* d_uy, double* d_T) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return engine_fields(ctx->e, 0, d_e, d_ux, d_uy, d_T, nullptr);
+}
+
+int rlbm_conserved(rlbm_ctx* ctx, double h_out[3]) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!h_out) return fail(RLBM_EINVAL, "NULL output");
+    Engine& E = ctx->e;
+    const int np = conserved_partials(E.lats[0].nx, E.lats[0].ny);
+    double* out3 = E.d_red + 3 * (size_t)E.lay.max_partials;
+    HIPCHK(launch_conserved(E.d_desc, 0, E.storage, E.stencil, E.lats[0].nx, E.lats[0].ny,
+                            E.parity(), E.d_red, np, out3, E.stream));
+    HIPCHK(hipMemcpyAsync(h_out, out3, 3 * sizeof(double), hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    return RLBM_OK;
+}
+
+int rlbm_get_populations(rlbm_ctx* ctx, double* d_out) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!d_out) return fail(RLBM_EINVAL, "NULL output");
+    Engine& E = ctx->e;
+    HIPCHK(launch_get_populations(E.d_desc, 0, E.storage, E.Q, E.lats[0].nx, E.lats[0].ny, d_out,
+                                  E.parity(), E.stream));
+    return RLBM_OK;
+}
+
+int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!d_in) return fail(RLBM_EINVAL, "NULL input");
+    Engine& E = ctx->e;
+    HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
+    E.step = 0;
+    HIPCHK(launch_set_populations(E.d_desc, 0, E.storage, E.Q, E.lats[0].nx, E.lats[0].ny, d_in,
+                                  E.parity(), E.stream));
+    return RLBM_OK;
+}
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static size_t spectrum_layout(int nx, int ny, size_t* o_z2, size_t* o_twx, size_t* o_twy,
+                              size_t* o_bins, size_t* o_part, size_t* o_out, int* max_bins) {
+    const size_t n = (size_t)nx * ny;
+    *max_bins = (int)std::ceil(std::sqrt((double)nx * nx / 4.0 + (double)ny * ny / 4.0)) + 2;
+    size_t off = align_up(sizeof(double2) * n);
+    *o_z2 = off; off = align_up(off + sizeof(double2) * n);
+    *o_twx = off; off = align_up(off + sizeof(double2) * (nx / 2 + 1));
+    *o_twy = off; off = align_up(off + sizeof(double2) * (ny / 2 + 1));
+    *o_bins = off; off = align_up(off + sizeof(double) * (*max_bins));
+    *o_part = off; off = align_up(off + sizeof(double) * spectrum_partials(nx, ny));
+    *o_out = off; off = align_up(off + sizeof(double) * 8);
+    return off;
+}
+
+int rlbm_spectrum_scratch_bytes(const rlbm_ctx* ctx, size_t* h_bytes) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!h_bytes) return fail(RLBM_EINVAL, "NULL output");
+    size_t a, b, c, d, e, f;
+    int mb;
+    *h_bytes = spectrum_layout(ctx->e.lats[0].nx, ctx->e.lats[0].ny, &a, &b, &c, &d, &e, &f, &mb);
+    return RLBM_OK;
+}
+
+int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double* h_Ek,
+                  int32_t nbins, double* h_enstrophy) {
+    if (int rc = check_ctx(ctx)) return rc;
+    Engine& E = ctx->e;
+    const int nx = E.lats[0].nx, ny = E.lats[0].ny;
+    if (!is_pow2(nx) || !is_pow2(ny))
+        return fail(RLBM_EUNSUPPORTED, "the spectrum needs power-of-two lattice sides");
+    if (!d_scratch || !h_Ek || nbins < 1) return fail(RLBM_EINVAL, "bad spectrum arguments");
+    size_t oz2, otx, oty, obins, opart, oout;
+    int max_bins;
+    const size_t need = spectrum_layout(nx, ny, &oz2, &otx, &oty, &obins, &opart, &oout, &max_bins);
+    if (scratch_bytes < need) return fail(RLBM_ENOSPACE, "spectrum scratch too small");
+    if ((uintptr_t)d_scratch % kAlign) return fail(RLBM_EINVAL, "scratch must be 256-byte aligned");
+    char* sc = (char*)d_scratch;
+    double2* z = (double2*)sc;
+    double2* z2 = (double2*)(sc + oz2);
+    std::vector<double2> twx(nx / 2 + 1), twy(ny / 2 + 1);
+    for (int m = 0; m < nx / 2; ++m)
+        twx[m] = make_double2(std::cos(2.0 * M_PI * m / nx), -std::sin(2.0 * M_PI * m / nx));
+    for (int m = 0; m < ny / 2; ++m)
+        twy[m] = make_double2(std::cos(2.0 * M_PI * m / ny), -std::sin(2.0 * M_PI * m / ny));
+    HIPCHK(hipMemcpyAsync(sc + otx, twx.data(), sizeof(double2) * twx.size(),
+                          hipMemcpyHostToDevice, E.stream));
+    HIPCHK(hipMemcpyAsync(sc + oty, twy.data(), sizeof(double2) * twy.size(),
+                          hipMemcpyHostToDevice, E.stream));
+    if (int rc = engine_fields(E, 0, nullptr, nullptr, nullptr, nullptr, z)) return rc;
+    double2* a = z;
+    double2* b = z2;
+    for (int ns = 1; ns < nx; ns *= 2) {   // rows (x)
+        HIPCHK(launch_fft_pass(a, b, (const double2*)(sc + otx), nx, ns, 1, nx, ny, E.stream));
+        std::swap(a, b);
+    }
+    for (int ns = 1; ns < ny; ns *= 2) {   // columns (y)
+        HIPCHK(launch_fft_pass(a, b, (const double2*)(sc + oty), ny, ns, nx, 1, nx, E.stream));
+        std::swap(a, b);
+    }
+    const int nb = std::min(nbins, max_bins);
+    HIPCHK(launch_spectrum_bins(a, nx, ny, nb, (double*)(sc + obins), (double*)(sc + opart),
+                                spectrum_partials(nx, ny), (double*)(sc + oout), E.stream));
+    for (int i = nb; i < nbins; ++i) h_Ek[i] = 0.0;
+    HIPCHK(hipMemcpyAsync(h_Ek, sc + obins, sizeof(double) * nb, hipMemcpyDeviceToHost, E.stream));
+    double zz = 0;
+    HIPCHK(hipMemcpyAsync(&zz, sc + oout, sizeof(double), hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    if (h_enstrophy) *h_enstrophy = 0.5 * zz;
+    return RLBM_OK;
+}
+
+int rlbm_state_bytes(const rlbm_ctx* ctx, size_t* h_bytes) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!h_bytes) return fail(RLBM_EINVAL, "NULL output");
+    const Engine& E = ctx->e;
+    *h_bytes = sizeof(SaveHeader) +
+               (size_t)E.Q * E.lats[0].nx * E.lats[0].ny * storage_bytes(E.storage);
+    return RLBM_OK;
+}
+
+int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes) {
+    size_t need = 0;
+    if (int rc = rlbm_state_bytes(ctx, &need)) return rc;
+    if (!h_buf) return fail(RLBM_EINVAL, "NULL buffer");
+    if (bytes < need) return fail(RLBM_ENOSPACE, "checkpoint buffer too small");
+    Engine& E = ctx->e;
+    SaveHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "RLBMSAV1", 8);
+    h.version = 1;
+    h.stencil = E.stencil;
+    h.storage = E.storage;
+    h.nx = E.lats[0].nx;
+    h.ny = E.lats[0].ny;
+    h.Q = E.Q;
+    h.step = E.step;
+    h.tau = E.taus[0];
+    h.cfl = E.lats[0].cfl;
+    h.amplitude = E.frc[0].amplitude;
+    h.k_lo = E.frc[0].k_lo;
+    h.k_hi = E.frc[0].k_hi;
+    h.seed = E.frc[0].seed;
+    std::memcpy(h_buf, &h, sizeof(h));
+    const int s = storage_bytes(E.storage);
+    const RealDesc& d = E.hdesc[0];
+    char* dst = (char*)h_buf + sizeof(h);
+    for (int q = 0; q < E.Q; ++q)
+        HIPCHK(hipMemcpy2DAsync(dst + (size_t)q * d.nx * d.ny * s, (size_t)d.nx * s,
+                                (const char*)d.buf[E.parity()] + (size_t)q * d.plane * s,
+                                (size_t)d.pitch * s, (size_t)d.nx * s, d.ny,
+                                hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    return RLBM_OK;
+}
+
+int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
+    size_t need = 0;
+    if (int rc = rlbm_state_bytes(ctx, &need)) return rc;
+    if (!h_buf || bytes < need) return fail(RLBM_EINVAL, "checkpoint buffer missing or short");
+    Engine& E = ctx->e;
+    SaveHeader h;
+    std::memcpy(&h, h_buf, sizeof(h));
+    if (std::memcmp(h.magic, "RLBMSAV1", 8) != 0 || h.version != 1)
+        return fail(RLBM_EINVAL, "not a checkpoint of this library");
+    if (h.stencil != E.stencil || h.storage != E.storage || h.nx != E.lats[0].nx ||
+        h.ny != E.lats[0].ny || h.Q != E.Q || h.tau != E.taus[0] || h.cfl != E.lats[0].cfl ||
+        h.amplitude != E.frc[0].amplitude || h.k_lo != E.frc[0].k_lo ||
+        h.k_hi != E.frc[0].k_hi || h.seed != E.frc[0].seed || h.step < 0)
+        return fail(RLBM_EINVAL, "checkpoint of another configuration");
+    E.step = h.step;
+    HIPCHK(launch_reset(E.d_step, h.step, E.d_flag, E.stream));
+    const int s = storage_bytes(E.storage);
+    const RealDesc& d = E.hdesc[0];
+    const char* src = (const char*)h_buf + sizeof(h);
+    for (int q = 0; q < E.Q; ++q)
+        HIPCHK(hipMemcpy2DAsync((char*)d.buf[E.parity()] + (size_t)q * d.plane * s,
+                                (size_t)d.pitch * s, src + (size_t)q * d.nx * d.ny * s,
+                                (size_t)d.nx * s, (size_t)d.nx * s, d.ny, hipMemcpyHostToDevice,
+                                E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    return RLBM_OK;
+}
+
+int rlbm_set_tile(rlbm_ctx* ctx, int32_t th) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (th != 1 && th != 2 && th != 4 && th != 8) return fail(RLBM_EINVAL, "tile height must be 1, 2, 4 or 8");
+    ctx->e.th = th;
+    return ctx->e.configure_tiles();
+}
+
+int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (steps < 1) return fail(RLBM_EINVAL, "steps must be >= 1");
+    Engine& E = ctx->e;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_th = E.th;
+    const int cand[4] = {1, 2, 4, 8};
+    for (int th : cand) {
+        E.th = th;
+        if (int rc = E.configure_tiles()) return rc;
+        if (int rc = E.run(1)) return rc;
+        HIPCHK(hipEventRecord(e0, E.stream));
+        if (int rc = E.run(steps)) return rc;
+        HIPCHK(hipEventRecord(e1, E.stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_th = th; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    E.th = best_th;
+    if (h_th) *h_th = best_th;
+    return E.configure_tiles();
+}
+
+int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (chunk < 0 || chunk > 4096) return fail(RLBM_EINVAL, "chunk must be in [0, 4096]");
+    ctx->e.graph_chunk = chunk;
+    return RLBM_OK;
+}
+
+void rlbm_destroy(rlbm_ctx* ctx) { delete ctx; }
+
+// ---- ensemble -----------------------------------------------------------------
+int rlbm_batch_workspace_bytes(int32_t n_real, const rlbm_lattice* lats, int stencil, int storage,
+                               const rlbm_forcing* forcings, size_t* h_bytes) {
+    return engine_bytes(n_real, lats, stencil, storage, forcings, h_bytes);
+}
+
+int rlbm_batch_init(rlbm_batch** out, int32_t n_real, const rlbm_lattice* lats,
+                    const double* taus, int stencil, const rlbm_forcing* forcings, int storage,
+                    void* d_workspace, size_t ws_bytes, void* hip_stream) {
+    if (!out) return fail(RLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    rlbm_batch* b = new (std::nothrow) rlbm_batch();
+    if (!b) return fail(RLBM_EINVAL, "out of host memory");
+    int rc = engine_init(b->e, n_real, lats, taus, stencil, forcings, storage, d_workspace,
+                         ws_bytes, hip_stream);
+    if (rc) { delete b; return rc; }
+    *out = b;
+    return RLBM_OK;
+}
+
+int rlbm_batch_set_state(rlbm_batch* b, int32_t r, const double* d_e, const double* d_ux,
+                         const double* d_uy) {
+    if (int rc = check_ctx(b)) return rc;
+    if (r < 0 || r >= b->e.n_real) return fail(RLBM_EINVAL, "realization out of range");
+    if (b->e.step != 0) return fail(RLBM_EINVAL, "set the ensemble state before the first step");
+    return engine_set_state(b->e, r, d_e, d_ux, d_uy, false);
+}
+
+int rlbm_batch_step(rlbm_batch* b, int64_t n) {
+    if (int rc = check_ctx(b)) return rc;
+    return b->e.run(n);
+}
+
+int rlbm_batch_check(rlbm_batch* b) {
+    if (int rc = check_ctx(b)) return rc;
+    return engine_check(b->e);
+}
+
+int rlbm_batch_fields(rlbm_batch* b, int32_t r, double* d_e, double* d_ux, double* d_uy,
+                      double* d_T) {
+    if (int rc = check_ctx(b)) return rc;
+    if (r < 0 || r >= b->e.n_real) return fail(RLBM_EINVAL, "realization out of range");
+    return engine_fields(b->e, r, d_e, d_ux, d_uy, d_T, nullptr);
+}
+
+int rlbm_batch_get_populations(rlbm_batch* b, int32_t r, double* d_out) {
+    if (int rc = check_ctx(b)) return rc;
+    if (r < 0 || r >= b->e.n_real || !d_out) return fail(RLBM_EINVAL, "bad arguments");
+    Engine& E = b->e;
+    HIPCHK(launch_get_populations(E.d_desc, r, E.storage, E.Q, E.lats[r].nx, E.lats[r].ny, d_out,
+                                  E.parity(), E.stream));
+    return RLBM_OK;
+}
+
+int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk) {
+    if (int rc = check_ctx(b)) return rc;
+    if (chunk < 0 || chunk > 4096) return fail(RLBM_EINVAL, "chunk must be in [0, 4096]");
+    b->e.graph_chunk = chunk;
+    return RLBM_OK;
+}
+
+void rlbm_batch_destroy(rlbm_batch* b) { delete b; }
+
+}  // extern "C"

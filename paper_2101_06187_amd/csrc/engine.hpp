@@ -1,0 +1,107 @@
+// Internal declarations shared by the device translation units and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "rlbm.h"
+#include "stencil.hpp"
+
+namespace rlbm {
+
+constexpr int kTileW = 64;            // sites per tile row = one wavefront
+constexpr int kMaxTileH = 8;
+
+// Per-lattice descriptor, resident in the workspace (read with scalar loads).
+struct RealDesc {
+    void* buf[2];                 // population buffers; step s reads buf[s & 1]
+    const double* tw64;           // [nx][2] cos, sin of 2 pi x / nx
+    const float* tw32;
+    double* g64;                  // force table [ny][K+1][4]: Px, Qx, Py, Qy
+    float* g32;
+    const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
+    const int* kptr;              // K+2 offsets into modes
+    long long plane;              // elements per population plane (pitch * ny)
+    int nx, ny, pitch;
+    int tiles_x, tiles_y;
+    int tile_begin;               // first tile of this lattice in the launch
+    int K;                        // largest |kx| of the driven modes; -1 unforced
+    int n_modes;
+    int realization;              // Philox counter word 2
+    int pad0;
+    uint64_t seed;
+    double amplitude;
+    double inv_tau;               // 1 / tau
+    double a[3];                  // interpolation weights cfl * |v| for 1, 2, 3
+                                  // non-zero cube components
+    double dt;                    // = cfl
+    float af[3];
+    float dtf;
+    float inv_tauf;
+    float pad1;
+};
+
+struct StepArgs {
+    const RealDesc* desc;         // device array of descriptors
+    const uint16_t* tile_real;    // tile -> lattice, NULL when there is one lattice
+    const int64_t* d_step;        // device step counter (base)
+    int* d_flag;                  // stability flag
+    int step_off;                 // this launch computes step *d_step + step_off
+    int n_tiles;
+    int th;                       // tile height (rows of 64 sites)
+};
+
+struct StepLaunch {
+    StepArgs args;
+    int stencil;
+    bool unit_cfl;
+    bool forced;
+    int grid;                     // persistent blocks
+    hipStream_t stream;
+};
+
+// Device translation units (one per storage form).
+hipError_t launch_step_f64(const StepLaunch& L);
+hipError_t launch_step_f32(const StepLaunch& L);
+hipError_t launch_step_f16s(const StepLaunch& L);
+hipError_t launch_step_bf16s(const StepLaunch& L);
+// Resident blocks per CU of a step-kernel configuration (occupancy query).
+int occ_f64(int stencil, bool unit_cfl, bool forced, int th);
+int occ_f32(int stencil, bool unit_cfl, bool forced, int th);
+int occ_f16s(int stencil, bool unit_cfl, bool forced, int th);
+int occ_bf16s(int stencil, bool unit_cfl, bool forced, int th);
+
+// Auxiliary kernels (kernels_aux.hip).
+hipError_t launch_force_table(const RealDesc* d_desc, int n_real, int max_rows, int max_k,
+                              const int64_t* d_step, int step_off, bool fp32,
+                              hipStream_t s);
+hipError_t launch_advance(int64_t* d_step, int64_t by, hipStream_t s);
+hipError_t launch_reset(int64_t* d_step, int64_t value, int* d_flag, hipStream_t s);
+hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int stencil,
+                            int nx, int ny, const double* e, const double* ux,
+                            const double* uy, int parity, hipStream_t s);
+hipError_t launch_set_populations(const RealDesc* d_desc, int r, int storage, int Q,
+                                  int nx, int ny, const double* in, int parity,
+                                  hipStream_t s);
+hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, int Q,
+                                  int nx, int ny, double* out, int parity,
+                                  hipStream_t s);
+hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil,
+                         bool unit_cfl, int nx, int ny, int parity, double* e,
+                         double* ux, double* uy, double* T, double2* z,
+                         int* d_flag, hipStream_t s);
+hipError_t launch_conserved(const RealDesc* d_desc, int r, int storage, int stencil,
+                            int nx, int ny, int parity, double* partials,
+                            int n_partials, double* out3, hipStream_t s);
+int conserved_partials(int nx, int ny);
+hipError_t launch_fft_pass(const double2* in, double2* out, const double2* tw, int n,
+                           int ns, int elem_stride, int batch_stride, int batch,
+                           hipStream_t s);
+hipError_t launch_spectrum_bins(const double2* Z, int nx, int ny, int nbins,
+                                double* out_bins, double* partials, int n_partials,
+                                double* out_z, hipStream_t s);
+int spectrum_partials(int nx, int ny);
+
+}  // namespace rlbm

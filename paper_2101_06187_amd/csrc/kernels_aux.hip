@@ -1,0 +1,500 @@
+// Auxiliary kernels: stirring-force table, step counter, initial state,
+// population import/export, macroscopic fields, conserved sums, FFT passes
+// and the shell-binned energy spectrum.
+#include "site.hpp"
+
+namespace rlbm {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
+// 32x32->64-bit multiplies by fixed odd constants, high/low halves mixed with
+// the other two counter words and the key, key bumped by Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+        const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+// Force table of one time step (Sec. V forcing, redrawn every step).  For row
+// y and k = |kx| in [0, K]:
+//   G_kx(y) = sum_{modes with this kx} A r (cos th, sin th) exp(i (2 pi ky y/ny + phi))
+//   P_c(k, y) = Re G_k + Re G_-k,  Q_c(k, y) = Im G_k - Im G_-k
+// so that F_c(x, y) = sum_k cos(2 pi k x/nx) P_c(k, y) - sin(2 pi k x/nx) Q_c(k, y).
+__global__ void force_table_kernel(const RealDesc* desc, const int64_t* d_step,
+                                   int step_off, int fp32) {
+    const RealDesc& D = desc[blockIdx.y];
+    if (D.K < 0) return;
+    const int K1 = D.K + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = idx / K1, k = idx - (idx / K1) * K1;
+    if (y >= D.ny) return;
+    const uint64_t step = (uint64_t)(*d_step + step_off);
+    const double two_pi = 2.0 * M_PI;
+    const double u32 = 2.3283064365386963e-10;   // 2^-32
+    double Px = 0, Qx = 0, Py = 0, Qy = 0;
+    for (int j = D.kptr[k]; j < D.kptr[k + 1]; ++j) {
+        const int4 md = D.modes[j];
+        uint32_t c[4] = {(uint32_t)md.z, (uint32_t)step, (uint32_t)D.realization, 0u};
+        philox4x32_10(c, (uint32_t)D.seed, (uint32_t)(D.seed >> 32));
+        const double rmag = ((double)c[0] + 0.5) * u32;
+        const double th = two_pi * (((double)c[1] + 0.5) * u32);
+        const double ph = two_pi * (((double)c[2] + 0.5) * u32);
+        double ct, st;
+        sincos(th, &st, &ct);
+        const long long jy = ((long long)md.y * y) % D.ny;
+        const double psi = two_pi * ((double)jy / (double)D.ny) + ph;
+        double cp, sp;
+        sincos(psi, &sp, &cp);
+        const double ax = D.amplitude * rmag * ct;
+        const double ay = D.amplitude * rmag * st;
+        const double sgn = md.x < 0 ? -1.0 : 1.0;
+        Px = fma(ax, cp, Px);
+        Qx = fma(sgn * ax, sp, Qx);
+        Py = fma(ay, cp, Py);
+        Qy = fma(sgn * ay, sp, Qy);
+    }
+    const size_t o = ((size_t)y * K1 + k) * 4;
+    D.g64[o + 0] = Px; D.g64[o + 1] = Qx; D.g64[o + 2] = Py; D.g64[o + 3] = Qy;
+    if (fp32) {
+        D.g32[o + 0] = (float)Px; D.g32[o + 1] = (float)Qx;
+        D.g32[o + 2] = (float)Py; D.g32[o + 3] = (float)Qy;
+    }
+}
+
+hipError_t launch_force_table(const RealDesc* d_desc, int n_real, int max_rows, int max_k,
+                              const int64_t* d_step, int step_off, bool fp32, hipStream_t s) {
+    const int n = max_rows * (max_k + 1);
+    dim3 grid((n + 255) / 256, n_real);
+    hipLaunchKernelGGL(force_table_kernel, grid, dim3(256), 0, s, d_desc, d_step, step_off,
+                       fp32 ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// step counter and stability flag
+// ---------------------------------------------------------------------------
+__global__ void advance_kernel(int64_t* d_step, int64_t by) {
+    if (threadIdx.x == 0) {
+        volatile int64_t* p = d_step;
+        *p = *p + by;
+    }
+}
+__global__ void reset_kernel(int64_t* d_step, int64_t value, int* d_flag) {
+    if (threadIdx.x == 0) {
+        volatile int64_t* p = d_step;
+        volatile int* q = d_flag;
+        *p = value;
+        *q = 0;
+    }
+}
+hipError_t launch_advance(int64_t* d_step, int64_t by, hipStream_t s) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, d_step, by);
+    return hipGetLastError();
+}
+hipError_t launch_reset(int64_t* d_step, int64_t value, int* d_flag, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, d_step, value, d_flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initial state (Sec. III C step (a)): F = F_eq(eps, beta)
+// ---------------------------------------------------------------------------
+template <class S, class St>
+__global__ void set_state_kernel(const RealDesc* desc, int r, const double* e,
+                                 const double* ux, const double* uy, int parity) {
+    const RealDesc& D = desc[r];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= D.nx) return;
+    const int i = y * D.nx + x;
+    double A0, B, C, gam;
+    const double bx = ux[i], by = uy[i];
+    eq_coeffs<St::D>(e[i], bx, by, A0, B, C, gam);
+    typename S::raw* dst = (typename S::raw*)D.buf[parity];
+    sfor<0, St::Q>([&](auto iq) {
+        constexpr int q = decltype(iq)::value;
+        constexpr double vx = dir_comp(St::dir[q], 0), vy = dir_comp(St::dir[q], 1);
+        const double t = vx * bx + vy * by;
+        const double F = fma(C, t * t, fma(B, t, A0));
+        dst[(long long)q * D.plane + (long long)y * D.pitch + x] = S::from64(F - S::shift);
+    });
+}
+
+template <class S, class St>
+__global__ void set_pop_kernel(const RealDesc* desc, int r, const double* in, int parity) {
+    const RealDesc& D = desc[r];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= D.nx) return;
+    typename S::raw* dst = (typename S::raw*)D.buf[parity];
+    for (int q = 0; q < St::Q; ++q)
+        dst[(long long)q * D.plane + (long long)y * D.pitch + x] =
+            S::from64(in[((long long)q * D.ny + y) * D.nx + x] - S::shift);
+}
+
+template <class S, class St>
+__global__ void get_pop_kernel(const RealDesc* desc, int r, double* out, int parity) {
+    const RealDesc& D = desc[r];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= D.nx) return;
+    const typename S::raw* src = (const typename S::raw*)D.buf[parity];
+    for (int q = 0; q < St::Q; ++q)
+        out[((long long)q * D.ny + y) * D.nx + x] =
+            S::to64(src[(long long)q * D.plane + (long long)y * D.pitch + x]) + S::shift;
+}
+
+// ---------------------------------------------------------------------------
+// fields: stage (c) of the step in FP64 -- stream the current populations,
+// form T^{mu nu}, solve the Landau frame.
+// ---------------------------------------------------------------------------
+template <class S, class St, bool UNIT>
+__global__ void fields_kernel(const RealDesc* desc, int r, int parity, double* e, double* ux,
+                              double* uy, double* T, double2* z, int* d_flag) {
+    const RealDesc& D = desc[r];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= D.nx) return;
+    const int nx = D.nx, ny = D.ny, pitch = D.pitch;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int rows[3] = {ym * pitch, y * pitch, yp * pitch};
+    const int cols[3] = {xm, x, xp};
+    uint32_t off[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i)
+            off[j][i] = (uint32_t)(rows[j] + cols[i]) * sizeof(typename S::raw);
+    double f[St::Q];
+    stream_pull<S, St, UNIT, double>((const char*)D.buf[parity],
+                                     D.plane * (long long)sizeof(typename S::raw), off,
+                                     D.a[0], D.a[1], D.a[2], f);
+    const Moments<double> m = moments<St, false>(f);
+    const double sh = (double)S::shift;
+    const double E = m.E + sh, Pxx = m.Pxx + sh / St::D, Pyy = m.Pyy + sh / St::D;
+    double eps, bx, by;
+    if (!landau64<St::D>(E, m.Jx, m.Jy, Pxx, m.Pxy, Pyy, eps, bx, by)) *d_flag = 1;
+    const size_t i = (size_t)y * nx + x, n = (size_t)nx * ny;
+    if (e) e[i] = eps;
+    if (ux) ux[i] = bx;
+    if (uy) uy[i] = by;
+    if (T) {
+        T[i] = E; T[n + i] = m.Jx; T[2 * n + i] = m.Jy;
+        T[3 * n + i] = Pxx; T[4 * n + i] = m.Pxy; T[5 * n + i] = Pyy;
+    }
+    if (z) z[i] = make_double2(bx, by);
+}
+
+// ---------------------------------------------------------------------------
+// conserved sums: sum over sites of T^00, T^0x, T^0y (stored populations),
+// FP64, fixed reduction order (per-thread sequential, wave shuffle tree,
+// block order, then one final block).
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* out) {
+    __shared__ double sm[kRedThreads / 64][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) sm[w][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double s = 0;
+            for (int k = 0; k < kRedThreads / 64; ++k) s += sm[k][c];
+            out[c] = s;
+        }
+    }
+}
+
+int conserved_partials(int nx, int ny) {
+    const long long n = (long long)nx * ny;
+    long long b = (n + kRedThreads - 1) / kRedThreads;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+template <class S, class St>
+__global__ void __launch_bounds__(kRedThreads)
+conserved_kernel(const RealDesc* desc, int r, int parity, double* partials) {
+    const RealDesc& D = desc[r];
+    const long long n = (long long)D.nx * D.ny;
+    const typename S::raw* src = (const typename S::raw*)D.buf[parity];
+    double acc[3] = {0, 0, 0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const int y = (int)(i / D.nx), x = (int)(i - (long long)y * D.nx);
+        double f[St::Q];
+        for (int q = 0; q < St::Q; ++q)
+            f[q] = S::to64(src[(long long)q * D.plane + (long long)y * D.pitch + x]);
+        const Moments<double> m = moments<St, false>(f);
+        acc[0] += m.E + (double)S::shift;
+        acc[1] += m.Jx;
+        acc[2] += m.Jy;
+    }
+    block_sum<3>(acc, partials + 3 * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+final_sum_kernel(const double* partials, int n_partials, int nv, double* out) {
+    for (int c = 0; c < nv; ++c) {
+        double v[1] = {0};
+        for (int i = threadIdx.x; i < n_partials; i += kRedThreads) v[0] += partials[i * nv + c];
+        block_sum<1>(v, out + c);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FFT: one radix-2 Stockham pass over a batch of strided 1-D sequences.
+// Pass with sub-transform size ns: a = in[j], c = in[j + n/2] * w^(k), k = j mod ns,
+// w = exp(-2 pi i / (2 ns)); out[(j/ns) 2 ns + k] = a + c, out[... + ns] = a - c.
+// After log2(n) passes the sequence is its DFT in natural order.
+// ---------------------------------------------------------------------------
+__global__ void fft_pass_kernel(const double2* in, double2* out, const double2* tw, int n,
+                                int ns, int es, int bs, int batch) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int half = n >> 1;
+    if (gid >= (long long)half * batch) return;
+    int j, bi;
+    if (es == 1) { bi = (int)(gid / half); j = (int)(gid - (long long)bi * half); }
+    else { j = (int)(gid / batch); bi = (int)(gid - (long long)j * batch); }
+    const int k = j % ns;
+    const size_t base = (size_t)bi * bs;
+    const double2 a = in[base + (size_t)j * es];
+    const double2 c0 = in[base + (size_t)(j + half) * es];
+    const double2 w = tw[(size_t)k * (n / (2 * ns))];
+    const double2 c = make_double2(c0.x * w.x - c0.y * w.y, c0.x * w.y + c0.y * w.x);
+    const int d = (j / ns) * 2 * ns + k;
+    out[base + (size_t)d * es] = make_double2(a.x + c.x, a.y + c.y);
+    out[base + (size_t)(d + ns) * es] = make_double2(a.x - c.x, a.y - c.y);
+}
+
+hipError_t launch_fft_pass(const double2* in, double2* out, const double2* tw, int n, int ns,
+                           int es, int bs, int batch, hipStream_t s) {
+    const long long work = (long long)(n / 2) * batch;
+    hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
+                       in, out, tw, n, ns, es, bs, batch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// spectrum.  Z = DFT(beta_x + i beta_y).  For real beta the shell sum of
+// 1/2 (|beta_hat_x|^2 + |beta_hat_y|^2) equals 1/2 sum_shell |Z(k)|^2 / (nx ny)^2
+// (the shells are closed under k -> -k).  One wavefront per bin; lane l takes
+// rows ky = ky_lo + l, ky_lo + l + 64, ...; mode k is in bin b iff
+// (2b - 1)^2 <= 4 |k|^2 < (2b + 1)^2 (exact integer test; no ties).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long isqrt_floor(long long v) {
+    if (v <= 0) return 0;
+    long long r = (long long)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+__device__ __forceinline__ double row_sum(const double2* Z, int nx, int ny, int ky, long long m_lo,
+                                          long long m_hi) {
+    const int iy = ky < 0 ? ky + ny : ky;
+    double s = 0;
+    for (long long m = m_lo; m <= m_hi; ++m) {
+        // kx = +m (valid if m < nx/2) and kx = -m (valid if m > 0 and m <= nx/2)
+        if (m < nx / 2) {
+            const double2 v = Z[(size_t)iy * nx + m];
+            s += v.x * v.x + v.y * v.y;
+        }
+        if (m > 0 && m <= nx / 2) {
+            const double2 v = Z[(size_t)iy * nx + (nx - m)];
+            s += v.x * v.x + v.y * v.y;
+        }
+    }
+    return s;
+}
+
+__global__ void __launch_bounds__(64)
+spectrum_bins_kernel(const double2* Z, int nx, int ny, int nbins, double* out) {
+    const int b = blockIdx.x;
+    if (b >= nbins) return;
+    const long long lo2 = (long long)(2 * b - 1) * (2 * b - 1);   // for b >= 1
+    const long long hi2 = (long long)(2 * b + 1) * (2 * b + 1);
+    const int kyl = max(-(b + 1), -ny / 2), kyh = min(b + 1, ny / 2 - 1);
+    double s = 0;
+    for (int ky = kyl + (int)threadIdx.x; ky <= kyh; ky += 64) {
+        const long long k2 = 4LL * ky * ky;
+        if (k2 >= hi2) continue;
+        // largest m with 4 (m^2 + ky^2) < hi2  <=>  4 m^2 <= hi2 - 1 - k2
+        const long long m_hi = isqrt_floor((hi2 - 1 - k2) / 4);
+        long long m_lo = 0;
+        if (b >= 1 && lo2 > k2) {
+            // smallest m with 4 m^2 >= lo2 - k2
+            const long long need = lo2 - k2;
+            m_lo = isqrt_floor((need + 3) / 4);
+            while (4 * m_lo * m_lo < need) ++m_lo;
+            while (m_lo > 0 && 4 * (m_lo - 1) * (m_lo - 1) >= need) --m_lo;
+        }
+        if (m_lo <= m_hi) s += row_sum(Z, nx, ny, ky, m_lo, min(m_hi, (long long)nx / 2));
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+        const double nn = (double)nx * (double)ny;
+        out[b] = 0.5 * s / (nn * nn);
+    }
+}
+
+int spectrum_partials(int nx, int ny) { return conserved_partials(nx, ny); }
+
+__global__ void __launch_bounds__(kRedThreads)
+enstrophy_kernel(const double2* Z, int nx, int ny, double* partials) {
+    const long long n = (long long)nx * ny;
+    const double inv = 1.0 / ((double)nx * (double)ny);
+    double acc[1] = {0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const int iy = (int)(i / nx), ix = (int)(i - (long long)iy * nx);
+        const int kx = ix < nx / 2 ? ix : ix - nx;
+        const int ky = iy < ny / 2 ? iy : iy - ny;
+        const double2 zk = Z[i];
+        const double2 zr = Z[(size_t)((ny - iy) % ny) * nx + (nx - ix) % nx];
+        // beta_hat_x = (Z(k) + conj Z(-k)) / 2,  beta_hat_y = -i (Z(k) - conj Z(-k)) / 2
+        const double bxr = 0.5 * (zk.x + zr.x) * inv, bxi = 0.5 * (zk.y - zr.y) * inv;
+        const double byr = 0.5 * (zk.y + zr.y) * inv, byi = -0.5 * (zk.x - zr.x) * inv;
+        const double ax = 2.0 * M_PI * kx / nx, ay = 2.0 * M_PI * ky / ny;
+        const double wr = ax * byr - ay * bxr, wi = ax * byi - ay * bxi;
+        acc[0] += wr * wr + wi * wi;
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
+hipError_t launch_spectrum_bins(const double2* Z, int nx, int ny, int nbins, double* out_bins,
+                                double* partials, int n_partials, double* out_z, hipStream_t s) {
+    hipLaunchKernelGGL(spectrum_bins_kernel, dim3(nbins), dim3(64), 0, s, Z, nx, ny, nbins,
+                       out_bins);
+    hipLaunchKernelGGL(enstrophy_kernel, dim3(n_partials), dim3(kRedThreads), 0, s, Z, nx, ny,
+                       partials);
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, n_partials,
+                       1, out_z);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch on (storage, stencil)
+// ---------------------------------------------------------------------------
+template <template <class, class> class Fn, class... Args>
+static hipError_t dispatch(int storage, int stencil, Args&&... args) {
+    auto go = [&](auto s_tag) -> hipError_t {
+        using S = decltype(s_tag);
+        if (stencil == RLBM_STENCIL_SPH26) return Fn<S, Sph26>::run(args...);
+        return Fn<S, Circ8>::run(args...);
+    };
+    switch (storage) {
+        case RLBM_F64: return go(StF64{});
+        case RLBM_F32: return go(StF32{});
+        case RLBM_F16S: return go(StF16S{});
+        default: return go(StBF16S{});
+    }
+}
+
+template <class S, class St>
+struct SetStateFn {
+    static hipError_t run(const RealDesc* d, int r, int nx, int ny, const double* e,
+                          const double* ux, const double* uy, int parity, hipStream_t s) {
+        hipLaunchKernelGGL((set_state_kernel<S, St>), dim3((nx + 127) / 128, ny), dim3(128), 0, s,
+                           d, r, e, ux, uy, parity);
+        return hipGetLastError();
+    }
+};
+template <class S, class St>
+struct SetPopFn {
+    static hipError_t run(const RealDesc* d, int r, int nx, int ny, const double* in, int parity,
+                          hipStream_t s) {
+        hipLaunchKernelGGL((set_pop_kernel<S, St>), dim3((nx + 127) / 128, ny), dim3(128), 0, s, d,
+                           r, in, parity);
+        return hipGetLastError();
+    }
+};
+template <class S, class St>
+struct GetPopFn {
+    static hipError_t run(const RealDesc* d, int r, int nx, int ny, double* out, int parity,
+                          hipStream_t s) {
+        hipLaunchKernelGGL((get_pop_kernel<S, St>), dim3((nx + 127) / 128, ny), dim3(128), 0, s, d,
+                           r, out, parity);
+        return hipGetLastError();
+    }
+};
+template <class S, class St>
+struct FieldsFn {
+    static hipError_t run(const RealDesc* d, int r, bool unit, int nx, int ny, int parity,
+                          double* e, double* ux, double* uy, double* T, double2* z, int* flag,
+                          hipStream_t s) {
+        const dim3 g((nx + 127) / 128, ny), b(128);
+        if (unit)
+            hipLaunchKernelGGL((fields_kernel<S, St, true>), g, b, 0, s, d, r, parity, e, ux, uy, T,
+                               z, flag);
+        else
+            hipLaunchKernelGGL((fields_kernel<S, St, false>), g, b, 0, s, d, r, parity, e, ux, uy,
+                               T, z, flag);
+        return hipGetLastError();
+    }
+};
+template <class S, class St>
+struct ConservedFn {
+    static hipError_t run(const RealDesc* d, int r, int parity, double* partials, int np,
+                          double* out3, hipStream_t s) {
+        hipLaunchKernelGGL((conserved_kernel<S, St>), dim3(np), dim3(kRedThreads), 0, s, d, r,
+                           parity, partials);
+        hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, np, 3,
+                           out3);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int stencil, int nx,
+                            int ny, const double* e, const double* ux, const double* uy,
+                            int parity, hipStream_t s) {
+    return dispatch<SetStateFn>(storage, stencil, d_desc, r, nx, ny, e, ux, uy, parity, s);
+}
+hipError_t launch_set_populations(const RealDesc* d_desc, int r, int storage, int Q, int nx,
+                                  int ny, const double* in, int parity, hipStream_t s) {
+    (void)Q;
+    return dispatch<SetPopFn>(storage, Q == 26 ? RLBM_STENCIL_SPH26 : RLBM_STENCIL_CIRC8, d_desc,
+                              r, nx, ny, in, parity, s);
+}
+hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, int Q, int nx,
+                                  int ny, double* out, int parity, hipStream_t s) {
+    return dispatch<GetPopFn>(storage, Q == 26 ? RLBM_STENCIL_SPH26 : RLBM_STENCIL_CIRC8, d_desc,
+                              r, nx, ny, out, parity, s);
+}
+hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil, bool unit_cfl,
+                         int nx, int ny, int parity, double* e, double* ux, double* uy,
+                         double* T, double2* z, int* d_flag, hipStream_t s) {
+    return dispatch<FieldsFn>(storage, stencil, d_desc, r, unit_cfl, nx, ny, parity, e, ux, uy,
+                              T, z, d_flag, s);
+}
+hipError_t launch_conserved(const RealDesc* d_desc, int r, int storage, int stencil, int nx,
+                            int ny, int parity, double* partials, int n_partials, double* out3,
+                            hipStream_t s) {
+    (void)nx; (void)ny;
+    return dispatch<ConservedFn>(storage, stencil, d_desc, r, parity, partials, n_partials, out3,
+                                 s);
+}
+
+}  // namespace rlbm

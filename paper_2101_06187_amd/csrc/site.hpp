@@ -1,0 +1,265 @@
+// Per-site device building blocks of the RLBM step: storage forms, pull
+// streaming, moments, the FP64 Landau-frame solve and the collision/force
+// update.  Shared by the step kernel and the auxiliary kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "engine.hpp"
+
+namespace rlbm {
+
+// ---------------------------------------------------------------------------
+// compile-time loop
+// ---------------------------------------------------------------------------
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// global address space and wave-uniform values.  Casting a uniform base to the
+// global address space lets the compiler address population planes as
+// (scalar 64-bit base) + (32-bit per-lane offset).
+// ---------------------------------------------------------------------------
+template <class X>
+using gp = __attribute__((address_space(1))) X*;
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni(long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint64_t uni(uint64_t v) { return (uint64_t)uni((long long)v); }
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+    return __longlong_as_double(uni(__double_as_longlong(v)));
+}
+template <class P>
+__device__ __forceinline__ P* uni(P* p) {
+    return (P*)uni((long long)(uintptr_t)p);
+}
+
+// ---------------------------------------------------------------------------
+// storage forms.  Registers hold f' = F - shift; memory holds raw(f').
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct StF64 {
+    using raw = double;
+    using T = double;
+    static constexpr int shift = 0;
+    static constexpr int id = RLBM_F64;
+    template <class P> __device__ static T ld(P p) { return *p; }
+    template <class P> __device__ static void st(P p, T v) { *p = v; }
+    __device__ static double to64(raw v) { return v; }
+    __device__ static raw from64(double v) { return v; }
+};
+struct StF32 {
+    using raw = float;
+    using T = float;
+    static constexpr int shift = 0;
+    static constexpr int id = RLBM_F32;
+    template <class P> __device__ static T ld(P p) { return *p; }
+    template <class P> __device__ static void st(P p, T v) { *p = v; }
+    __device__ static double to64(raw v) { return (double)v; }
+    __device__ static raw from64(double v) { return (float)v; }
+};
+struct StF16S {
+    using raw = _Float16;
+    using T = float;
+    static constexpr int shift = 1;
+    static constexpr int id = RLBM_F16S;
+    template <class P> __device__ static T ld(P p) { return (float)*p; }
+    template <class P> __device__ static void st(P p, T v) { *p = (_Float16)v; }
+    __device__ static double to64(raw v) { return (double)(float)v; }
+    __device__ static raw from64(double v) { return (_Float16)(float)v; }
+};
+struct StBF16S {
+    using raw = uint16_t;
+    using T = float;
+    static constexpr int shift = 1;
+    static constexpr int id = RLBM_BF16S;
+    template <class P> __device__ static T ld(P p) { return __uint_as_float((uint32_t)*p << 16); }
+    template <class P> __device__ static void st(P p, T v) { *p = f32_to_bf16_rne(v); }
+    __device__ static double to64(raw v) { return (double)__uint_as_float((uint32_t)v << 16); }
+    __device__ static raw from64(double v) { return f32_to_bf16_rne((float)v); }
+};
+
+// ---------------------------------------------------------------------------
+// pull streaming by linear interpolation (Sec. III B), periodic lattice.
+// off[j][i] is the byte offset of node (x + i - 1, y + j - 1) within a plane.
+// The population of direction c arriving at x comes from x - cfl * v: for
+// c_x > 0 it lies between x - 1 (weight a) and x (weight 1 - a), a = cfl |v_x|.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T lerp(T p, T q, T t) { return fma(t, q - p, p); }
+
+template <class S, class St, bool UNIT, class T>
+__device__ __forceinline__ void stream_pull(const char* base, long long plane_bytes,
+                                            const uint32_t (&off)[3][3], T a1, T a2, T a3,
+                                            T (&f)[St::Q]) {
+    using raw = typename S::raw;
+    sfor<0, St::Q>([&](auto iq) {
+        constexpr int q = decltype(iq)::value;
+        constexpr Dir d = St::dir[q];
+        constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+        constexpr int ux = d.cx > 0 ? 0 : (d.cx < 0 ? 2 : 1);   // upstream column index
+        constexpr int uy = d.cy > 0 ? 0 : (d.cy < 0 ? 2 : 1);   // upstream row index
+        const gp<const char> pq = (gp<const char>)(base + (long long)q * plane_bytes);
+        auto L = [&](int j, int i) -> T { return (T)S::ld((gp<const raw>)(pq + off[j][i])); };
+        const T a = n == 1 ? a1 : (n == 2 ? a2 : a3);
+        if constexpr (d.cx == 0 && d.cy == 0) {
+            f[q] = L(1, 1);
+        } else if constexpr (d.cy == 0) {
+            if constexpr (UNIT && n == 1) f[q] = L(1, ux);
+            else f[q] = lerp(L(1, 1), L(1, ux), a);
+        } else if constexpr (d.cx == 0) {
+            if constexpr (UNIT && n == 1) f[q] = L(uy, 1);
+            else f[q] = lerp(L(1, 1), L(uy, 1), a);
+        } else {
+            const T p0 = lerp(L(1, 1), L(1, ux), a);
+            const T p1 = lerp(L(uy, 1), L(uy, ux), a);
+            f[q] = lerp(p0, p1, a);
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// moments (Sec. III A): E = sum w F, J = sum w F v, Pi = sum w F v v and, for
+// the force, R = sum w F v v v (in-plane components), from shifted registers.
+// Pair sums S = F(+u) + F(-u) carry the even moments, D = F(+u) - F(-u) the
+// odd ones.
+// ---------------------------------------------------------------------------
+template <class T>
+struct Moments {
+    T E, Jx, Jy, Pxx, Pxy, Pyy, Rxxx, Rxxy, Rxyy, Ryyy;
+};
+
+template <class St, bool WITH_R, class T>
+__device__ __forceinline__ Moments<T> moments(const T (&f)[St::Q]) {
+    Moments<T> m{};
+    sfor<0, St::NC>([&](auto ic) {
+        constexpr DirClass C = St::cls[ic];
+        constexpr double um = comp_mag(C.ncomp);
+        constexpr double ux = C.sx * um, uy = C.sy * um;
+        T Sp = f[C.first];
+        sfor<1, C.nplus>([&](auto i) { Sp += f[C.first + decltype(i)::value]; });
+        T S = Sp, Dd = Sp;
+        if constexpr (C.nminus > 0) {
+            T Sm = f[C.first + C.nplus];
+            sfor<1, C.nminus>([&](auto i) { Sm += f[C.first + C.nplus + decltype(i)::value]; });
+            S = Sp + Sm;
+            Dd = Sp - Sm;
+        }
+        m.E = fma((T)C.w, S, m.E);
+        if constexpr (ux != 0.0) {
+            m.Pxx = fma((T)(C.w * ux * ux), S, m.Pxx);
+            m.Jx = fma((T)(C.w * ux), Dd, m.Jx);
+        }
+        if constexpr (uy != 0.0) {
+            m.Pyy = fma((T)(C.w * uy * uy), S, m.Pyy);
+            m.Jy = fma((T)(C.w * uy), Dd, m.Jy);
+        }
+        if constexpr (ux != 0.0 && uy != 0.0) m.Pxy = fma((T)(C.w * ux * uy), S, m.Pxy);
+        if constexpr (WITH_R) {
+            if constexpr (ux != 0.0) m.Rxxx = fma((T)(C.w * ux * ux * ux), Dd, m.Rxxx);
+            if constexpr (ux != 0.0 && uy != 0.0) {
+                m.Rxxy = fma((T)(C.w * ux * ux * uy), Dd, m.Rxxy);
+                m.Rxyy = fma((T)(C.w * ux * uy * uy), Dd, m.Rxyy);
+            }
+            if constexpr (uy != 0.0) m.Ryyy = fma((T)(C.w * uy * uy * uy), Dd, m.Ryyy);
+        }
+    });
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 helpers: reciprocal and reciprocal square root from the hardware
+// estimates refined by Newton steps (each step doubles the correct bits).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
+// ---------------------------------------------------------------------------
+// Landau frame (Sec. III A/B).  For a state without out-of-plane momentum the
+// condition T^{mu nu} u_nu = -eps u^mu reduces to
+//     (eps I + Pi) beta = J,   eps = E - J . beta,
+// i.e. eps is the root of g(eps) = eps - E + J^T (eps I + Pi)^-1 J with
+// g'(eps) = 1 - |beta|^2 > 0.  Newton's method from the small-velocity
+// estimate eps0 = E - |J|^2 D / ((D+1) E).  Returns false if it does not
+// converge or the result is unphysical.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ bool landau64(double E, double Jx, double Jy, double Pxx,
+                                         double Pxy, double Pyy, double& eps, double& bx,
+                                         double& by) {
+    const double J2 = Jx * Jx + Jy * Jy;
+    double e = E - J2 * ((double)D / (D + 1)) * rcp64(E);
+    bool ok = false;
+    for (int it = 0; it < 16; ++it) {
+        const double a = e + Pxx, c = e + Pyy;
+        const double inv = rcp64(fma(a, c, -Pxy * Pxy));
+        bx = (c * Jx - Pxy * Jy) * inv;
+        by = (a * Jy - Pxy * Jx) * inv;
+        const double g = e - E + Jx * bx + Jy * by;
+        const double gp = 1.0 - bx * bx - by * by;
+        const double de = g * rcp64(gp);
+        e -= de;
+        if (!(fabs(de) > 4e-16 * fabs(e))) { ok = true; break; }
+    }
+    const double a = e + Pxx, c = e + Pyy;
+    const double inv = rcp64(fma(a, c, -Pxy * Pxy));
+    bx = (c * Jx - Pxy * Jy) * inv;
+    by = (a * Jy - Pxy * Jx) * inv;
+    eps = e;
+    const double b2 = bx * bx + by * by;
+    return ok && e > 0.0 && b2 < 1.0 && isfinite(e) && isfinite(b2);
+}
+
+// Equilibrium coefficients (Sec. III B, second-order projection of the
+// Juettner distribution): F_eq(v) = A0 + B t + C t^2 with t = beta . v,
+//   T00 = (eps + P) gamma^2 - P,  P = eps / D,
+//   B = D (eps + P) gamma^2,  C = D (D+2)/2 (eps + P) gamma^2,
+//   A0 = T00 - C beta^2 / D.
+template <int D>
+__device__ __forceinline__ void eq_coeffs(double eps, double bx, double by, double& A0,
+                                          double& B, double& C, double& gamma) {
+    const double b2 = bx * bx + by * by;
+    const double g2 = rcp64(1.0 - b2);
+    gamma = rsqrt64(1.0 - b2);
+    constexpr double invD = 1.0 / D;
+    const double hp = eps * ((D + 1.0) / D) * g2;     // (eps + P) gamma^2
+    B = D * hp;
+    C = (D * (D + 2) * 0.5) * hp;
+    A0 = hp - eps * invD - C * b2 * invD;
+}
+
+}  // namespace rlbm

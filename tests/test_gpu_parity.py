@@ -1,0 +1,320 @@
+"""GPU parity of the HIP RLBM step against the FP64 oracle, through the C ABI.
+
+Tolerances (normwise, see gpu_helpers.field_errors):
+  F64 storage  -- 1e-12 on every field and on the populations (both sides
+                  FP64; differences come only from rounding order, FMA
+                  contraction and the Newton vs eigen-solver Landau routes);
+  F32 storage  -- FP32 arithmetic and storage: populations within 4e-6 of the
+                  oracle after one step from identical inputs;
+  F16S/BF16S   -- the stored deviation F - 1 is rounded to 11 / 8 significant
+                  bits: |dF| <= 2^-11 |F - 1| (2^-8 for BF16) + 4e-6.
+"""
+import numpy as np
+import pytest
+
+import paper_2101_06187_amd as rl
+from oracle import diagnostics as odiag
+from oracle import rlbm as orlbm
+from oracle import stencil as ostencil
+import workloads
+
+from gpu_helpers import (dev, field_errors, gather_patches, gpu_fields, host, lib_to_oracle,
+                         oracle_step_at, oracle_to_lib, rel, sample_sites, say)
+
+pytestmark = pytest.mark.gpu
+
+SPH = ostencil.sph26()
+
+
+def _oracle_fields(F_or, st, cfl=1.0):
+    e, bx, by, T6 = odiag.fields(F_or, st, cfl)
+    return e, bx, by, T6
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_set_state_matches_oracle_equilibrium(storage):
+    say("set_state", storage)
+    e, bx, by = workloads.noisy_rest(40, 70, 0.05, seed=3)
+    lat = rl.Lattice(70, 40, 0.7, storage=storage)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    F = lib_to_oracle(host(lat.populations()))
+    Fo = orlbm.set_state(e, bx, by, SPH)
+    tol = 1e-15 if storage == "F64" else 1e-7
+    assert rel(F, Fo) < tol
+    errs = field_errors(gpu_fields(lat), _oracle_fields(Fo, SPH))
+    say(errs)
+    assert max(errs.values()) < (1e-12 if storage == "F64" else 1e-6)
+
+
+@pytest.mark.parametrize("shape", [(5, 3), (130, 5), (64, 9), (67, 2)])
+@pytest.mark.parametrize("forced", [False, True])
+@pytest.mark.parametrize("cfl", [1.0, 0.8])
+def test_one_step_random_populations_f64(shape, forced, cfl):
+    """Random (non-equilibrium, z-mirror-symmetric) populations on small and
+    ragged lattices: one step, every population, against the oracle."""
+    nx, ny = shape
+    say("one step", shape, forced, cfl)
+    F0 = workloads.random_populations(SPH.v, ny, nx, seed=nx * 7 + ny, spread=0.3)
+    force = dict(amplitude=3e-3, k_lo=1.0, k_hi=2.3, seed=5) if forced else None
+    if forced and (nx < 6 or ny < 6):
+        force = dict(amplitude=3e-3, k_lo=1.0, k_hi=1.0, seed=5)
+        if nx < 3 or ny < 3:
+            pytest.skip("lattice too small for a k = 1 forcing mode")
+    fr = rl.Forcing(force["amplitude"], force["k_lo"], force["k_hi"], force["seed"]) if force else None
+    lat = rl.Lattice(nx, ny, 0.62, storage="F64", cfl=cfl, forcing=fr)
+    lat.set_populations(dev(oracle_to_lib(F0)))
+    lat.step(1)
+    F1 = lib_to_oracle(host(lat.populations()))
+    F1o = orlbm.step(F0, SPH, 0.62, cfl, force, 0)
+    err = rel(F1, F1o)
+    say("populations err", err)
+    assert err < 1e-13
+    assert lat.check() == rl.OK
+
+
+def test_shear_wave_parity_and_decay():
+    """Shear-wave workload (64 x 64, tau 1, unforced): 200 steps compared
+    field by field with the oracle; 1000 steps on the GPU must decay at the
+    linear-theory rate and conserve T^{0 mu}."""
+    n = 64
+    e, bx, by = workloads.shear_wave(n, 0.01)
+    lat = rl.Lattice(n, n, 1.0, storage="F64")
+    lat.set_state(dev(e), dev(bx), dev(by))
+    c0 = lat.conserved()
+    lat.step(200)
+    Fo = orlbm.run(orlbm.set_state(e, bx, by, SPH), SPH, 1.0, 200)
+    errs = field_errors(gpu_fields(lat), _oracle_fields(Fo, SPH))
+    say("shear 200 steps", errs)
+    assert max(errs.values()) < 1e-12
+    a200 = np.abs(np.fft.rfft(host(lat.fields()[1])[:, 0])[1])
+    lat.step(800)
+    a1000 = np.abs(np.fft.rfft(host(lat.fields()[1])[:, 0])[1])
+    from test_oracle_shear_wave import shear_eigenvalue
+    lam = abs(shear_eigenvalue(SPH, 1.0, 2 * np.pi / n))
+    rate = (a1000 / a200) ** (1 / 800)
+    say("decay rate", rate, "linear theory", lam)
+    assert abs(rate / lam - 1) < 1e-6
+    c1 = lat.conserved()
+    say("conservation drift", c1 - c0)
+    assert abs(c1[0] - c0[0]) < 1e-13 * c0[0]
+    assert np.abs(c1[1:] - c0[1:]).max() < 1e-13 * c0[0]
+
+
+def _forced512(storage, steps):
+    n = 512
+    e, bx, by = workloads.noisy_rest(n, n, 0.005, seed=1)
+    fr = rl.Forcing(1e-5, 4.0, 6.0, 2)
+    lat = rl.Lattice(n, n, 0.55, storage=storage, forcing=fr)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    lat.step(steps)
+    F = orlbm.set_state(e, bx, by, SPH)
+    F = orlbm.run(F, SPH, 0.55, steps,
+                  force=dict(amplitude=1e-5, k_lo=4.0, k_hi=6.0, seed=2))
+    return lat, F
+
+
+def test_forced512_short_horizon_f64():
+    """512 x 512 forced workload (tau 0.55, shell [4, 6], A = 1e-5, seeds 1/2):
+    3 steps, all fields within 1e-12 of the oracle."""
+    lat, Fo = _forced512("F64", 3)
+    errs = field_errors(gpu_fields(lat), _oracle_fields(Fo, SPH))
+    say("forced512 F64", errs)
+    assert max(errs.values()) < 1e-12
+    assert rel(lib_to_oracle(host(lat.populations())), Fo) < 1e-13
+
+
+@pytest.mark.parametrize("storage,tol_eps,tol_beta",
+                         [("F32", 1e-6, 2e-4), ("F16S", 5e-5, 2e-2), ("BF16S", 5e-4, 1e-1)])
+def test_forced512_short_horizon_reduced_storage(storage, tol_eps, tol_beta):
+    """The same workload with reduced population storage: stated field error."""
+    lat, Fo = _forced512(storage, 3)
+    errs = field_errors(gpu_fields(lat), _oracle_fields(Fo, SPH))
+    say("forced512", storage, errs)
+    assert errs["eps"] < tol_eps
+    assert errs["beta_x"] < tol_beta and errs["beta_y"] < tol_beta
+
+
+@pytest.mark.parametrize("storage,n,shell,amp,tau", [
+    ("F32", 2048, (8.0, 12.0), 1e-5, 0.52),
+    ("F16S", 2048, (8.0, 12.0), 1e-5, 0.52),
+    ("BF16S", 2048, (8.0, 12.0), 1e-5, 0.52),
+    ("F32", 8192, (32.0, 40.0), 2e-6, 0.505),
+    ("F16S", 8192, (32.0, 40.0), 2e-6, 0.505),
+])
+def test_full_size_sampled_one_step(storage, n, shell, amp, tau):
+    """Full-size workloads in the benchmark's launch configuration: after a
+    few steps, one more step is checked at sampled sites (incl. the four
+    corners) against the oracle applied to the 3x3 neighbourhood."""
+    import torch
+    say("full size", storage, n)
+    sigma, seed = (0.005, 1) if n == 2048 else (0.002, 3)
+    e, bx, by = workloads.noisy_rest(n, n, sigma, seed)
+    fr = rl.Forcing(amp, shell[0], shell[1], 2)
+    lat = rl.Lattice(n, n, tau, storage=storage, forcing=fr)
+    lat.set_graph_chunk(8)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    del e, bx, by
+    lat.step(8)
+    xs, ys = sample_sites(n, n, 48, seed=n)
+    F_before = lat.populations()
+    P = gather_patches(F_before, xs, ys)
+    del F_before
+    torch.cuda.empty_cache()
+    lat.step(1)
+    F_after = lat.populations()
+    got = host(F_after[:, torch.as_tensor(ys, device="cuda:0"), torch.as_tensor(xs, device="cuda:0")])
+    del F_after
+    torch.cuda.empty_cache()
+    P_or = lib_to_oracle(P.reshape(P.shape[0], -1)).reshape(P.shape)
+    want = oracle_step_at(P_or, SPH, tau, 1.0,
+                          force=dict(amplitude=amp, k_lo=shell[0], k_hi=shell[1], seed=2),
+                          step_index=8, sites=(xs, ys), nxy=(n, n))
+    got_or = lib_to_oracle(got)
+    d = np.abs(got_or - want)
+    bits = {"F32": None, "F16S": 2.0 ** -11, "BF16S": 2.0 ** -8}[storage]
+    bound = 4e-6 + (0 if bits is None else bits * np.abs(want - 1.0))
+    say("max |dF|", d.max(), "max bound", bound.max() if np.ndim(bound) else bound)
+    assert np.all(d <= bound)
+    assert lat.check() == rl.OK
+    lat.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_tile_shape_does_not_change_results(storage):
+    """Per-site arithmetic is independent of the launch shape: bitwise."""
+    n = 96
+    e, bx, by = workloads.noisy_rest(n + 8, n, 0.01, seed=4)
+    fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
+    ref = None
+    for th in (1, 2, 4, 8):
+        lat = rl.Lattice(n, n + 8, 0.56, storage=storage, forcing=fr)
+        lat.set_tile(th)
+        lat.set_state(dev(e), dev(bx), dev(by))
+        lat.step(5)
+        F = host(lat.populations())
+        if ref is None:
+            ref = F
+        else:
+            assert np.array_equal(F, ref), th
+
+
+def test_graph_replay_matches_direct_launches():
+    """Captured-graph stepping equals direct launches bitwise, replay after
+    replay, with eager work and synchronisations in between."""
+    import torch
+    n = 128
+    e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=6)
+    fr = rl.Forcing(1e-4, 3.0, 6.0, 9)
+    a = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    b = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    for lat in (a, b):
+        lat.set_state(dev(e), dev(bx), dev(by))
+    b.set_graph_chunk(4)
+    for rep in range(4):
+        a.step(8)
+        b.step(8)          # two graph replays
+        junk = torch.randn(1000, device="cuda:0").sum()   # eager work in between
+        torch.cuda.synchronize()
+        assert np.array_equal(host(a.populations()), host(b.populations())), rep
+        assert a.steps == b.steps == 8 * (rep + 1)
+    del junk
+
+
+def test_checkpoint_resume_is_bitwise():
+    n = 64
+    e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=8)
+    fr = rl.Forcing(1e-4, 2.0, 4.0, 12)
+    a = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    a.set_state(dev(e), dev(bx), dev(by))
+    a.step(7)
+    blob = a.save()
+    a.step(9)
+    b = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    b.load(blob)
+    assert b.steps == 7
+    b.step(9)
+    assert np.array_equal(host(a.populations()), host(b.populations()))
+    c = rl.Lattice(n, n, 0.61, storage="F32", forcing=fr)
+    with pytest.raises(rl.RlbmError):
+        c.load(blob)
+
+
+def test_conserved_matches_oracle():
+    e, bx, by = workloads.noisy_rest(48, 80, 0.02, seed=2)
+    lat = rl.Lattice(80, 48, 0.7, storage="F64")
+    lat.set_state(dev(e), dev(bx), dev(by))
+    lat.step(3)
+    Fo = orlbm.run(orlbm.set_state(e, bx, by, SPH), SPH, 0.7, 3)
+    c = lat.conserved()
+    co = odiag.conserved(Fo, SPH)
+    assert np.abs(c - co).max() < 1e-12 * co[0]
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_spectrum_matches_oracle(n):
+    e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=5)
+    lat = rl.Lattice(n, n, 0.6, storage="F64", forcing=rl.Forcing(1e-4, 2, 4, 1))
+    lat.set_state(dev(e), dev(bx), dev(by))
+    lat.step(2)
+    nb = n
+    Ek, Z = lat.spectrum(nb)
+    _, gx, gy, _ = gpu_fields(lat)
+    Eo, Zo = odiag.spectrum(gx, gy, nb)
+    say("spectrum", rel(Ek, Eo), abs(Z - Zo) / Zo)
+    assert rel(Ek, Eo) < 1e-12
+    assert abs(Z - Zo) < 1e-12 * Zo
+
+
+def test_spectrum_rejects_non_power_of_two():
+    lat = rl.Lattice(48, 48, 0.6)
+    with pytest.raises(rl.RlbmError) as ex:
+        lat.spectrum(10)
+    assert ex.value.code == rl.EUNSUPPORTED
+
+
+def test_unstable_state_is_flagged():
+    """Condition forced from the host: a lattice whose populations carry a
+    negative energy density; every kernel exits normally, the flag trips."""
+    n = 16
+    F = -np.ones((26, n, n))
+    lat = rl.Lattice(n, n, 0.6, storage="F64")
+    lat.set_populations(dev(F))
+    assert lat.check() == rl.OK
+    lat.step(1)
+    assert lat.check() == rl.EUNSTABLE
+
+
+def test_circ8_parity():
+    st = ostencil.circ8()
+    F0 = workloads.random_populations(st.v, 20, 36, seed=3, spread=0.3, z_mirror=False)
+    lat = rl.Lattice(36, 20, 0.66, stencil="CIRC8", storage="F64",
+                     forcing=rl.Forcing(2e-3, 1.0, 3.0, 4))
+    lat.set_populations(dev(oracle_to_lib(F0, "CIRC8")))
+    lat.step(2)
+    F2 = lib_to_oracle(host(lat.populations()), "CIRC8")
+    F2o = orlbm.run(F0, st, 0.66, 2, force=dict(amplitude=2e-3, k_lo=1.0, k_hi=3.0, seed=4))
+    assert rel(F2, F2o) < 1e-13
+
+
+def test_ensemble_matches_oracle():
+    """Independent lattices of different sizes and tau in one persistent
+    launch per step; realization r draws its force with counter word r."""
+    sizes = [(64, 64), (128, 64), (64, 128), (96, 40)]
+    taus = [0.55, 0.7, 0.61, 0.8]
+    frs = [rl.Forcing(1e-4, 2.0, 4.0, r) for r in range(4)]
+    ens = rl.Ensemble(sizes, taus, storage="F64", forcings=frs)
+    inits = []
+    for r, (nx, ny) in enumerate(sizes):
+        e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=r)
+        inits.append((e, bx, by))
+        ens.set_state(r, dev(e), dev(bx), dev(by))
+    ens.step(3)
+    for r, (nx, ny) in enumerate(sizes):
+        F = orlbm.set_state(*inits[r], SPH)
+        F = orlbm.run(F, SPH, taus[r], 3,
+                      force=dict(amplitude=1e-4, k_lo=2.0, k_hi=4.0, seed=r), realization=r)
+        got = lib_to_oracle(host(ens.populations(r)))
+        say("ensemble", r, rel(got, F))
+        assert rel(got, F) < 1e-13
+    assert ens.check() == rl.OK

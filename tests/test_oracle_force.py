@@ -141,3 +141,10 @@ def test_force_field_zero_average_and_redrawn():
 def test_nyquist_shell_rejected():
     with pytest.raises(ValueError):
         forcing.modes(16, 16, 6, 8)
+
+
+def test_force_at_points_equals_field():
+    fx, fy = forcing.force_field(40, 36, 2e-3, 3, 6, 4, 11, 2)
+    ys, xs = np.meshgrid(np.arange(36), np.arange(40), indexing="ij")
+    gx, gy = forcing.force_at(40, 36, 2e-3, 3, 6, 4, 11, xs, ys, 2)
+    assert np.abs(gx - fx).max() < 1e-17 and np.abs(gy - fy).max() < 1e-17
