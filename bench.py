@@ -1,0 +1,271 @@
+"""Benchmark of the fused RLBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (the metric's FP32-vs-FP64 configuration): 512 x 512 periodic
+lattice, spherical 26-direction stencil, tau = 0.55, eps = 1 and
+beta ~ N(0, 0.005^2) per component (seed 1), stirring force on the shell
+|k| in [4, 6] with amplitude 1e-5 redrawn every step from Philox (seed 2).
+A step is the whole hot path: force table + fused stream / moments / FP64
+Landau / equilibrium / collision / force / store.  Inputs are resident in
+HBM before timing starts.
+
+The headline value is the FP32-population step in MLUPS.  The same line
+carries the FP64, F16S and BF16S forms of the step (MLUPS, kernel GB/s and
+their field error against the FP64 path after the same steps), the same
+kernel on HBM-resident lattices (2048^2 and 8192^2), the roofline of the
+FP32 step kernel (per-launch duration from HIP events around every launch)
+and the FP64 NumPy oracle timed on the host cores for a bounded sample.
+Everything except the JSON line goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+Q = 26
+BYTES = {"F64": 8, "F32": 4, "F16S": 2, "BF16S": 2}
+METRIC = "MLUPS + HBM GB/s (% peak): FP32/FP16-storage vs FP64 step at stated field error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """Hash of the sources the step kernel is built from (for counter data)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2101_06187_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch of the FP32 step kernel on this workload from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_src_sha") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def make_lattice(rl, wl, storage, torch):
+    import workloads
+    A, klo, khi, fseed = wl.forcing
+    lat = rl.Lattice(wl.n, wl.n, wl.tau, storage=storage,
+                     forcing=rl.Forcing(A, klo, khi, fseed))
+    e, bx, by = workloads.initial_fields(wl)
+    dev = lambda a: torch.from_numpy(a).to("cuda:0")  # noqa: E731
+    lat.set_state(dev(e), dev(bx), dev(by))
+    del e, bx, by
+    return lat
+
+
+def time_steps(lat, torch, steps, warmup, chunk):
+    lat.set_graph_chunk(chunk)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    lat.step(steps)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def field_error(a, b):
+    """Normwise error of fields a against reference b (eps; beta as a vector)."""
+    ea, xa, ya, _ = [t.cpu().numpy() for t in a]
+    eb, xb, yb, _ = [t.cpu().numpy() for t in b]
+    vmax = max(np.abs(xb).max(), np.abs(yb).max())
+    return {"eps": float(np.abs(ea - eb).max() / np.abs(eb).max()),
+            "beta": float(max(np.abs(xa - xb).max(), np.abs(ya - yb).max()) / vmax)}
+
+
+def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n):
+    lat = make_lattice(rl, wl, storage, torch)
+    ms = time_steps(lat, torch, steps, warmup, chunk)
+    kms = lat.profile_step_kernel(prof_n)
+    sites = wl.n * wl.n
+    algo = 2 * Q * BYTES[storage] * sites
+    out = {
+        "storage": storage,
+        "ms_per_step": ms,
+        "mlups": sites / (ms * 1e-3) / 1e6,
+        "kernel_ms": kms,
+        "kernel_gbs": algo / (kms * 1e-3) / 1e9,
+        "step_gbs": algo / (ms * 1e-3) / 1e9,
+        "steps_done": warmup + steps + prof_n,
+    }
+    out["kernel_frac_hbm_peak"] = out["kernel_gbs"] / HBM_PEAK_GBS
+    return lat, out
+
+
+def cpu_baseline(wl, n_steps):
+    """The FP64 oracle on the same workload, single thread, a few steps."""
+    from threadpoolctl import threadpool_limits
+    import workloads
+    from oracle import rlbm as orlbm
+    from oracle import stencil as ostencil
+    st = ostencil.sph26()
+    A, klo, khi, fseed = wl.forcing
+    force = dict(amplitude=A, k_lo=klo, k_hi=khi, seed=fseed)
+    e, bx, by = workloads.initial_fields(wl)
+    with threadpool_limits(limits=1):
+        F = orlbm.set_state(e, bx, by, st)
+        t = time.perf_counter()
+        for s in range(n_steps):
+            F = orlbm.step(F, st, wl.tau, 1.0, force, s)
+        dt = time.perf_counter() - t
+    return {"value": wl.n * wl.n * n_steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_steps} steps of the {wl.n}x{wl.n} forced workload, FP64 NumPy "
+                      f"oracle on one host core ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the HBM-resident 2048^2 / 8192^2 lines")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--only", default=None, metavar="WORKLOAD:STORAGE",
+                    help="time one form only (e.g. forced2048:F32), for profiler runs")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run a plain device copy of this many bytes 3 times "
+                         "(counter calibration under rocprofv3 --pmc)")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2101_06187_amd as rl
+    import workloads
+
+    rl.lib()
+    log("device:", torch.cuda.get_device_name(0))
+    if a.copy_bytes:
+        n = a.copy_bytes // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy: 3 x {4 * n} bytes")
+        del src, dst
+    if a.only:
+        name, storage = a.only.split(":")
+        w = workloads.WORKLOADS[name]
+        lat, r = run_form(rl, torch, w, storage, a.steps, a.warmup, 50, min(a.steps, 200))
+        r["unstable"] = lat.check() != rl.OK
+        log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms'] * 1e3:.2f} us "
+            f"= {r['kernel_gbs']:.0f} GB/s")
+        print(json.dumps({"only": a.only, **r}), flush=True)
+        return
+    wl = workloads.WORKLOADS["forced512"]
+    chunk = 50
+
+    forms = {}
+    lats = {}
+    for storage in ("F32", "F64", "F16S", "BF16S"):
+        lat, r = run_form(rl, torch, wl, storage, a.steps, a.warmup, chunk, 500)
+        lats[storage] = lat
+        forms[storage] = r
+        log(f"{storage}: {r['mlups']:.0f} MLUPS, {r['ms_per_step'] * 1e3:.2f} us/step, "
+            f"kernel {r['kernel_ms'] * 1e3:.2f} us = {r['kernel_gbs']:.0f} GB/s")
+    ref = lats["F64"].fields()
+    for storage in ("F32", "F16S", "BF16S"):
+        forms[storage]["field_error_vs_f64"] = field_error(lats[storage].fields(), ref)
+        log(storage, "field error vs F64 path:", forms[storage]["field_error_vs_f64"])
+    for storage in ("F32", "F64", "F16S", "BF16S"):
+        forms[storage]["unstable"] = lats[storage].check() != rl.OK
+        lats[storage].close()
+    del lats, ref
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not a.no_extra:
+        for name, storages, steps in (("forced2048", ("F32", "F16S", "BF16S"), 300),
+                                      ("forced8192", ("F32", "F16S"), 60)):
+            w = workloads.WORKLOADS[name]
+            extra[name] = {}
+            for storage in storages:
+                lat, r = run_form(rl, torch, w, storage, steps, 20, 20, 20)
+                r["unstable"] = lat.check() != rl.OK
+                lat.close()
+                del lat
+                torch.cuda.empty_cache()
+                extra[name][storage] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms",
+                                                          "kernel_gbs", "kernel_frac_hbm_peak",
+                                                          "unstable")}
+                log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
+                    f"({100 * r['kernel_frac_hbm_peak']:.1f}% of HBM peak)")
+
+    head = forms["F32"]
+    sites = wl.n * wl.n
+    per_launch = 2 * Q * BYTES["F32"] * sites
+    traffic = committed_traffic()
+    roofline = {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": head["kernel_gbs"] / HBM_PEAK_GBS,
+                "traffic": traffic,
+                "kernel": "rlbm::step_kernel<StF32, Sph26, unit cfl, forced>",
+                "algorithmic_bytes_per_launch": per_launch,
+                "kernel_ms": head["kernel_ms"]}
+
+    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_steps)
+    if cpu:
+        log("cpu baseline:", cpu)
+
+    line = {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "forced512: 512x512 periodic, SPH26 stencil, tau 0.55, "
+                               "beta~N(0,0.005^2) seed 1, force shell |k| in [4,6] "
+                               "amplitude 1e-5 Philox seed 2, FP32 populations",
+                   "lattice": [wl.n, wl.n], "storage": "F32", "parallelism": "single GPU",
+                   "graph_chunk": chunk},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "hbm_resident": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,13 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th);
  * (0 = direct launches).  Results are identical either way.               */
 int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk);
 
+/* Advance n >= 1 steps exactly like rlbm_step, launching directly, with a
+ * HIP event recorded on the context's stream just before and just after
+ * every launch of the fused step kernel; synchronises and writes the mean
+ * step-kernel duration in milliseconds to *h_ms (the force-table kernel of
+ * each step is outside the bracket).  For roofline measurement.           */
+int rlbm_profile_step_kernel(rlbm_ctx* ctx, int64_t n, double* h_ms);
+
 void rlbm_destroy(rlbm_ctx* ctx);
 
 /* ---- ensemble of independent lattices --------------------------------------- */

@@ -85,6 +85,7 @@ SIGNATURES = [
     ("rlbm_set_tile", _I, [_P, _I32]),
     ("rlbm_autotune", _I, [_P, _I32, _P]),
     ("rlbm_set_graph_chunk", _I, [_P, _I32]),
+    ("rlbm_profile_step_kernel", _I, [_P, _I64, _P]),
     ("rlbm_destroy", None, [_P]),
     ("rlbm_batch_workspace_bytes", _I, [_I32, _P, _I, _I, _P, _P]),
     ("rlbm_batch_init", _I, [_P, _I32, _P, _P, _I, _P, _I, _P, _SZ, _P]),
@@ -270,6 +271,13 @@ class Lattice:
 
     def set_graph_chunk(self, chunk):
         _check(lib().rlbm_set_graph_chunk(self._ctx, int(chunk)))
+
+    def profile_step_kernel(self, n):
+        """Advance n steps; mean duration (ms) of the fused step kernel, from
+        HIP events recorded around each launch on the library's stream."""
+        ms = ctypes.c_double()
+        _check(lib().rlbm_profile_step_kernel(self._ctx, int(n), ctypes.byref(ms)))
+        return ms.value
 
     def close(self):
         if self._ctx:

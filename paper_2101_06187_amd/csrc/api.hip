@@ -94,8 +94,8 @@ int pitch_of(int nx) { return (nx + kTileW - 1) / kTileW * kTileW; }
 // partials, tile map, then per lattice: two population buffers, twiddles,
 // force tables, mode tables).
 struct Layout {
-    size_t ctl = 0, desc = 0, red = 0, tiles = 0, total = 0;
-    struct Per { size_t buf0, buf1, tw64, tw32, g64, g32, modes, kptr; };
+    size_t ctl = 0, desc = 0, red = 0, tiles = 0, gitems = 0, total = 0;
+    struct Per { size_t buf0, buf1, twx, twy, g0, g1, modes, kptr; };
     std::vector<Per> per;
     int max_partials = 0;
 };
@@ -106,27 +106,31 @@ int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storag
     size_t off = 0;
     L.ctl = off; off = align_up(off + 64);
     L.desc = off; off = align_up(off + sizeof(RealDesc) * (size_t)n_real);
+    const size_t cs = storage == RLBM_F64 ? sizeof(double) : sizeof(float);   // compute type
     int maxp = 1;
-    long long tiles1 = 0;
+    long long tiles1 = 0, gitems1 = 0;
     for (int r = 0; r < n_real; ++r) {
         maxp = std::max(maxp, conserved_partials(lats[r].nx, lats[r].ny));
         tiles1 += (long long)((lats[r].nx + kTileW - 1) / kTileW) * lats[r].ny;
+        gitems1 += (long long)(mts[r].K + 1) * ((lats[r].ny + kTileW - 1) / kTileW);
     }
     L.max_partials = maxp;
     L.red = off; off = align_up(off + sizeof(double) * (3 * (size_t)maxp + 8));
     L.tiles = off;
     if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)tiles1);
+    L.gitems = off;
+    if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)gitems1);
     L.per.resize(n_real);
     for (int r = 0; r < n_real; ++r) {
         const size_t plane = (size_t)pitch_of(lats[r].nx) * lats[r].ny;
         auto& P = L.per[r];
         P.buf0 = off; off = align_up(off + plane * Q * s);
         P.buf1 = off; off = align_up(off + plane * Q * s);
-        P.tw64 = off; off = align_up(off + sizeof(double) * 2 * lats[r].nx);
-        P.tw32 = off; off = align_up(off + sizeof(float) * 2 * lats[r].nx);
+        P.twx = off; off = align_up(off + cs * 2 * lats[r].nx);
+        P.twy = off; off = align_up(off + cs * 2 * lats[r].ny);
         const size_t g = (size_t)lats[r].ny * (mts[r].K + 1) * 4;
-        P.g64 = off; off = align_up(off + sizeof(double) * g);
-        P.g32 = off; off = align_up(off + sizeof(float) * g);
+        P.g0 = off; off = align_up(off + cs * g);
+        P.g1 = off; off = align_up(off + cs * g);
         P.modes = off; off = align_up(off + sizeof(int4) * mts[r].modes.size());
         P.kptr = off; off = align_up(off + sizeof(int) * mts[r].kptr.size());
     }
@@ -154,8 +158,9 @@ struct Engine {
     int* d_flag = nullptr;
     double* d_red = nullptr;
     uint16_t* d_tiles = nullptr;
+    uint16_t* d_gitems = nullptr;
+    int n_gitems = 0;
     bool unit_cfl = true, any_forced = false;
-    int max_rows = 0, max_k = -1;
     int th = 4, n_tiles = 0, grid = 0, cus = 0;
     int64_t step = 0;
     int graph_chunk = 0;
@@ -186,7 +191,9 @@ struct Engine {
     // tiles of height th, tile map, persistent grid
     int configure_tiles() {
         n_tiles = 0;
-        std::vector<uint16_t> map;
+        n_gitems = 0;
+        std::vector<uint16_t> map, gmap;
+        const int rows = kTileW * th;                 // rows per force-table item
         for (int r = 0; r < n_real; ++r) {
             RealDesc& d = hdesc[r];
             d.tiles_x = (d.nx + kTileW - 1) / kTileW;
@@ -194,11 +201,18 @@ struct Engine {
             d.tile_begin = n_tiles;
             n_tiles += d.tiles_x * d.tiles_y;
             if (n_real > 1) map.insert(map.end(), (size_t)d.tiles_x * d.tiles_y, (uint16_t)r);
+            d.gitem_begin = n_gitems;
+            const int items = d.K >= 0 ? (d.K + 1) * ((d.ny + rows - 1) / rows) : 0;
+            n_gitems += items;
+            if (n_real > 1) gmap.insert(gmap.end(), (size_t)items, (uint16_t)r);
         }
         HIPCHK(hipMemcpyAsync(d_desc, hdesc.data(), sizeof(RealDesc) * n_real,
                               hipMemcpyHostToDevice, stream));
         if (n_real > 1)
             HIPCHK(hipMemcpyAsync(d_tiles, map.data(), sizeof(uint16_t) * map.size(),
+                                  hipMemcpyHostToDevice, stream));
+        if (n_real > 1 && !gmap.empty())
+            HIPCHK(hipMemcpyAsync(d_gitems, gmap.data(), sizeof(uint16_t) * gmap.size(),
                                   hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
         const int per_cu = occupancy();
@@ -207,29 +221,76 @@ struct Engine {
         return RLBM_OK;
     }
 
-    hipError_t launch_one(int step_off) {
+    // n steps with events around every step-kernel launch; mean duration in ms
+    int profile(int64_t n, double* avg_ms) {
+        if (n < 1 || n > 100000) return fail(RLBM_EINVAL, "n must be in [1, 100000]");
+        std::vector<hipEvent_t> ev(2 * n, nullptr);
+        int rc = RLBM_OK;
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) { rc = fail(RLBM_EHIP, "hipEventCreate failed"); break; }
+        for (int64_t i = 0; i < n && rc == RLBM_OK; ++i) {
+            StepLaunch L = make_launch((int)i, stream);
+            if (launch_on(L, ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+                rc = fail(RLBM_EHIP, "launch failed while profiling");
+        }
+        if (rc == RLBM_OK && launch_advance(d_step, n, stream) != hipSuccess)
+            rc = fail(RLBM_EHIP, "launch failed while profiling");
+        if (rc == RLBM_OK) step += n;
+        double total = 0;
+        if (rc == RLBM_OK && hipEventSynchronize(ev[2 * n - 1]) != hipSuccess)
+            rc = fail(RLBM_EHIP, "hipEventSynchronize failed");
+        for (int64_t i = 0; i < n && rc == RLBM_OK; ++i) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+                rc = fail(RLBM_EHIP, "hipEventElapsedTime failed");
+            total += ms;
+        }
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (rc == RLBM_OK && avg_ms) *avg_ms = total / (double)n;
+        return rc;
+    }
+
+    StepLaunch make_launch(int step_off, hipStream_t s) const {
         StepLaunch L;
         L.args.desc = d_desc;
         L.args.tile_real = n_real > 1 ? d_tiles : nullptr;
+        L.args.gitem_real = n_real > 1 ? d_gitems : nullptr;
         L.args.d_step = d_step;
         L.args.d_flag = d_flag;
         L.args.step_off = step_off;
         L.args.n_tiles = n_tiles;
+        L.args.n_gitems = any_forced ? n_gitems : 0;
         L.args.th = th;
         L.stencil = stencil;
         L.unit_cfl = unit_cfl;
         L.forced = any_forced;
         L.grid = grid;
-        L.stream = stream;
+        L.stream = s;
+        return L;
+    }
+
+    hipError_t launch_one(int step_off) {
+        StepLaunch L = make_launch(step_off, stream);
         return launch_on(L);
     }
 
-    hipError_t launch_on(StepLaunch& L) {
-        if (any_forced) {
-            hipError_t e = launch_force_table(d_desc, n_real, max_rows, max_k, d_step,
-                                              L.args.step_off, storage != RLBM_F64, L.stream);
-            if (e != hipSuccess) return e;
-        }
+    // one launch per step: the step kernel also builds the next step's force table
+    hipError_t launch_on(StepLaunch& L, hipEvent_t before = nullptr, hipEvent_t after = nullptr) {
+        L.ev_start = before;
+        L.ev_stop = after;
+        return launch_step_kernel(L);
+    }
+
+    // force table of the current step (after the populations were set or loaded)
+    int prime_force_table() {
+        if (!any_forced) return RLBM_OK;
+        StepLaunch L = make_launch(0, stream);
+        HIPCHK(launch_force_table(L.args, storage != RLBM_F64, stream));
+        return RLBM_OK;
+    }
+
+    hipError_t launch_step_kernel(StepLaunch& L) {
         switch (storage) {
             case RLBM_F64: return launch_step_f64(L);
             case RLBM_F32: return launch_step_f32(L);
@@ -244,19 +305,7 @@ struct Engine {
         HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
         for (int i = 0; i < chunk && err == hipSuccess; ++i) {
-            StepLaunch L;
-            L.args.desc = d_desc;
-            L.args.tile_real = n_real > 1 ? d_tiles : nullptr;
-            L.args.d_step = d_step;
-            L.args.d_flag = d_flag;
-            L.args.step_off = i;
-            L.args.n_tiles = n_tiles;
-            L.args.th = th;
-            L.stencil = stencil;
-            L.unit_cfl = unit_cfl;
-            L.forced = any_forced;
-            L.grid = grid;
-            L.stream = cap_stream;
+            StepLaunch L = make_launch(i, cap_stream);
             err = launch_on(L);
         }
         if (err == hipSuccess) err = launch_advance(d_step, chunk, cap_stream);
@@ -361,11 +410,10 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
     E.d_desc = (RealDesc*)(E.ws + E.lay.desc);
     E.d_red = (double*)(E.ws + E.lay.red);
     E.d_tiles = (uint16_t*)(E.ws + E.lay.tiles);
+    E.d_gitems = (uint16_t*)(E.ws + E.lay.gitems);
     E.hdesc.assign(n_real, RealDesc{});
     E.unit_cfl = true;
     E.any_forced = false;
-    E.max_rows = 0;
-    E.max_k = -1;
     const int s = storage_bytes(storage);
     for (int r = 0; r < n_real; ++r) {
         const auto& P = E.lay.per[r];
@@ -374,10 +422,10 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         std::memset(&d, 0, sizeof(d));
         d.buf[0] = E.ws + P.buf0;
         d.buf[1] = E.ws + P.buf1;
-        d.tw64 = (const double*)(E.ws + P.tw64);
-        d.tw32 = (const float*)(E.ws + P.tw32);
-        d.g64 = (double*)(E.ws + P.g64);
-        d.g32 = (float*)(E.ws + P.g32);
+        d.twx = E.ws + P.twx;
+        d.twy = E.ws + P.twy;
+        d.g[0] = E.ws + P.g0;
+        d.g[1] = E.ws + P.g1;
         d.modes = (const int4*)(E.ws + P.modes);
         d.kptr = (const int*)(E.ws + P.kptr);
         d.nx = lat.nx;
@@ -389,6 +437,7 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         d.realization = r;
         d.seed = E.frc[r].seed;
         d.amplitude = E.frc[r].amplitude;
+        d.amplitudef = (float)d.amplitude;
         d.inv_tau = 1.0 / taus[r];
         d.a[0] = lat.cfl;
         d.a[1] = lat.cfl * kInvSqrt2;
@@ -400,28 +449,34 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         if (lat.cfl != 1.0) E.unit_cfl = false;
         if (d.K >= 0) {
             E.any_forced = true;
-            E.max_rows = std::max(E.max_rows, lat.ny);
-            E.max_k = std::max(E.max_k, d.K);
         }
         (void)s;
     }
     // twiddles and mode tables (host -> workspace, synchronous at init)
-    for (int r = 0; r < n_real; ++r) {
-        const auto& P = E.lay.per[r];
-        const int nx = lats[r].nx;
-        std::vector<double> t64(2 * nx);
-        std::vector<float> t32(2 * nx);
-        for (int x = 0; x < nx; ++x) {
-            const double a = 2.0 * M_PI * (double)x / (double)nx;
+    const bool f64 = storage == RLBM_F64;
+    auto upload_tw = [&](size_t off, int n) -> int {
+        std::vector<double> t64(2 * n);
+        std::vector<float> t32(2 * n);
+        for (int x = 0; x < n; ++x) {
+            const double a = 2.0 * M_PI * (double)x / (double)n;
             t64[2 * x] = std::cos(a);
             t64[2 * x + 1] = std::sin(a);
             t32[2 * x] = (float)t64[2 * x];
             t32[2 * x + 1] = (float)t64[2 * x + 1];
         }
-        HIPCHK(hipMemcpyAsync(E.ws + P.tw64, t64.data(), sizeof(double) * t64.size(),
-                              hipMemcpyHostToDevice, E.stream));
-        HIPCHK(hipMemcpyAsync(E.ws + P.tw32, t32.data(), sizeof(float) * t32.size(),
-                              hipMemcpyHostToDevice, E.stream));
+        if (f64)
+            HIPCHK(hipMemcpyAsync(E.ws + off, t64.data(), sizeof(double) * t64.size(),
+                                  hipMemcpyHostToDevice, E.stream));
+        else
+            HIPCHK(hipMemcpyAsync(E.ws + off, t32.data(), sizeof(float) * t32.size(),
+                                  hipMemcpyHostToDevice, E.stream));
+        HIPCHK(hipStreamSynchronize(E.stream));
+        return RLBM_OK;
+    };
+    for (int r = 0; r < n_real; ++r) {
+        const auto& P = E.lay.per[r];
+        if (int rc2 = upload_tw(P.twx, lats[r].nx)) return rc2;
+        if (int rc2 = upload_tw(P.twy, lats[r].ny)) return rc2;
         if (!E.mts[r].modes.empty()) {
             HIPCHK(hipMemcpyAsync(E.ws + P.modes, E.mts[r].modes.data(),
                                   sizeof(int4) * E.mts[r].modes.size(), hipMemcpyHostToDevice,
@@ -448,7 +503,7 @@ int engine_set_state(Engine& E, int r, const double* d_e, const double* d_ux,
     }
     HIPCHK(launch_set_state(E.d_desc, r, E.storage, E.stencil, E.lats[r].nx, E.lats[r].ny, d_e,
                             d_ux, d_uy, E.parity(), E.stream));
-    return RLBM_OK;
+    return E.prime_force_table();
 }
 
 int engine_fields(Engine& E, int r, double* d_e, double* d_ux, double* d_uy, double* d_T,
@@ -612,7 +667,7 @@ int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in) {
     E.step = 0;
     HIPCHK(launch_set_populations(E.d_desc, 0, E.storage, E.Q, E.lats[0].nx, E.lats[0].ny, d_in,
                                   E.parity(), E.stream));
-    return RLBM_OK;
+    return E.prime_force_table();
 }
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -756,6 +811,7 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
                                 (size_t)d.pitch * s, src + (size_t)q * d.nx * d.ny * s,
                                 (size_t)d.nx * s, (size_t)d.nx * s, d.ny, hipMemcpyHostToDevice,
                                 E.stream));
+    if (int rc = E.prime_force_table()) return rc;
     HIPCHK(hipStreamSynchronize(E.stream));
     return RLBM_OK;
 }
@@ -801,6 +857,12 @@ int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk) {
     if (chunk < 0 || chunk > 4096) return fail(RLBM_EINVAL, "chunk must be in [0, 4096]");
     ctx->e.graph_chunk = chunk;
     return RLBM_OK;
+}
+
+int rlbm_profile_step_kernel(rlbm_ctx* ctx, int64_t n, double* h_ms) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!h_ms) return fail(RLBM_EINVAL, "NULL output");
+    return ctx->e.profile(n, h_ms);
 }
 
 void rlbm_destroy(rlbm_ctx* ctx) { delete ctx; }

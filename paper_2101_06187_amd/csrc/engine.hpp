@@ -14,13 +14,14 @@ namespace rlbm {
 constexpr int kTileW = 64;            // sites per tile row = one wavefront
 constexpr int kMaxTileH = 8;
 
-// Per-lattice descriptor, resident in the workspace (read with scalar loads).
+// Per-lattice descriptor, resident in the workspace; every field is read
+// once per tile and made wave-uniform.
 struct RealDesc {
     void* buf[2];                 // population buffers; step s reads buf[s & 1]
-    const double* tw64;           // [nx][2] cos, sin of 2 pi x / nx
-    const float* tw32;
-    double* g64;                  // force table [ny][K+1][4]: Px, Qx, Py, Qy
-    float* g32;
+    const void* twx;              // [nx][2] cos, sin of 2 pi x / nx (compute type)
+    const void* twy;              // [ny][2] cos, sin of 2 pi y / ny (compute type)
+    void* g[2];                   // force table of step s in g[s & 1]:
+                                  //   [ny][K+1][4] = Px, Qx, Py, Qy (compute type)
     const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
     const int* kptr;              // K+2 offsets into modes
     long long plane;              // elements per population plane (pitch * ny)
@@ -30,7 +31,7 @@ struct RealDesc {
     int K;                        // largest |kx| of the driven modes; -1 unforced
     int n_modes;
     int realization;              // Philox counter word 2
-    int pad0;
+    int gitem_begin;              // first force-table work item of this lattice
     uint64_t seed;
     double amplitude;
     double inv_tau;               // 1 / tau
@@ -40,16 +41,19 @@ struct RealDesc {
     float af[3];
     float dtf;
     float inv_tauf;
-    float pad1;
+    float amplitudef;
 };
 
+// A force-table work item covers one |kx| = k and 64 * th consecutive rows.
 struct StepArgs {
     const RealDesc* desc;         // device array of descriptors
     const uint16_t* tile_real;    // tile -> lattice, NULL when there is one lattice
+    const uint16_t* gitem_real;   // force item -> lattice, NULL when there is one lattice
     const int64_t* d_step;        // device step counter (base)
     int* d_flag;                  // stability flag
     int step_off;                 // this launch computes step *d_step + step_off
     int n_tiles;
+    int n_gitems;                 // force-table items of the next step (0: unforced)
     int th;                       // tile height (rows of 64 sites)
 };
 
@@ -60,6 +64,8 @@ struct StepLaunch {
     bool forced;
     int grid;                     // persistent blocks
     hipStream_t stream;
+    hipEvent_t ev_start = nullptr;  // optional: kernel start/stop timestamps
+    hipEvent_t ev_stop = nullptr;
 };
 
 // Device translation units (one per storage form).
@@ -73,10 +79,8 @@ int occ_f32(int stencil, bool unit_cfl, bool forced, int th);
 int occ_f16s(int stencil, bool unit_cfl, bool forced, int th);
 int occ_bf16s(int stencil, bool unit_cfl, bool forced, int th);
 
-// Auxiliary kernels (kernels_aux.hip).
-hipError_t launch_force_table(const RealDesc* d_desc, int n_real, int max_rows, int max_k,
-                              const int64_t* d_step, int step_off, bool fp32,
-                              hipStream_t s);
+// Force table of the current step (kernels_aux.hip), for initial states.
+hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_advance(int64_t* d_step, int64_t by, hipStream_t s);
 hipError_t launch_reset(int64_t* d_step, int64_t value, int* d_flag, hipStream_t s);
 hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int stencil,

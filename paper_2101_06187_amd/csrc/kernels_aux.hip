@@ -6,76 +6,22 @@
 namespace rlbm {
 
 // ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
-// 32x32->64-bit multiplies by fixed odd constants, high/low halves mixed with
-// the other two counter words and the key, key bumped by Weyl constants.
+// force table of the current step (the step kernel builds the table of the
+// step after it; this fills the first one after a state is set or loaded)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) { k0 += W0; k1 += W1; }
-        const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
-        const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0;
-        const uint32_t n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    }
+template <class T>
+__global__ void force_table_kernel(StepArgs A) {
+    const int u = blockIdx.x;
+    const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
+    const RealDesc& Dsc = A.desc[r];
+    force_item<T>(Dsc, u - uni(Dsc.gitem_begin), *A.d_step + A.step_off, kTileW * A.th);
 }
 
-// Force table of one time step (Sec. V forcing, redrawn every step).  For row
-// y and k = |kx| in [0, K]:
-//   G_kx(y) = sum_{modes with this kx} A r (cos th, sin th) exp(i (2 pi ky y/ny + phi))
-//   P_c(k, y) = Re G_k + Re G_-k,  Q_c(k, y) = Im G_k - Im G_-k
-// so that F_c(x, y) = sum_k cos(2 pi k x/nx) P_c(k, y) - sin(2 pi k x/nx) Q_c(k, y).
-__global__ void force_table_kernel(const RealDesc* desc, const int64_t* d_step,
-                                   int step_off, int fp32) {
-    const RealDesc& D = desc[blockIdx.y];
-    if (D.K < 0) return;
-    const int K1 = D.K + 1;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = idx / K1, k = idx - (idx / K1) * K1;
-    if (y >= D.ny) return;
-    const uint64_t step = (uint64_t)(*d_step + step_off);
-    const double two_pi = 2.0 * M_PI;
-    const double u32 = 2.3283064365386963e-10;   // 2^-32
-    double Px = 0, Qx = 0, Py = 0, Qy = 0;
-    for (int j = D.kptr[k]; j < D.kptr[k + 1]; ++j) {
-        const int4 md = D.modes[j];
-        uint32_t c[4] = {(uint32_t)md.z, (uint32_t)step, (uint32_t)D.realization, 0u};
-        philox4x32_10(c, (uint32_t)D.seed, (uint32_t)(D.seed >> 32));
-        const double rmag = ((double)c[0] + 0.5) * u32;
-        const double th = two_pi * (((double)c[1] + 0.5) * u32);
-        const double ph = two_pi * (((double)c[2] + 0.5) * u32);
-        double ct, st;
-        sincos(th, &st, &ct);
-        const long long jy = ((long long)md.y * y) % D.ny;
-        const double psi = two_pi * ((double)jy / (double)D.ny) + ph;
-        double cp, sp;
-        sincos(psi, &sp, &cp);
-        const double ax = D.amplitude * rmag * ct;
-        const double ay = D.amplitude * rmag * st;
-        const double sgn = md.x < 0 ? -1.0 : 1.0;
-        Px = fma(ax, cp, Px);
-        Qx = fma(sgn * ax, sp, Qx);
-        Py = fma(ay, cp, Py);
-        Qy = fma(sgn * ay, sp, Qy);
-    }
-    const size_t o = ((size_t)y * K1 + k) * 4;
-    D.g64[o + 0] = Px; D.g64[o + 1] = Qx; D.g64[o + 2] = Py; D.g64[o + 3] = Qy;
-    if (fp32) {
-        D.g32[o + 0] = (float)Px; D.g32[o + 1] = (float)Qx;
-        D.g32[o + 2] = (float)Py; D.g32[o + 3] = (float)Qy;
-    }
-}
-
-hipError_t launch_force_table(const RealDesc* d_desc, int n_real, int max_rows, int max_k,
-                              const int64_t* d_step, int step_off, bool fp32, hipStream_t s) {
-    const int n = max_rows * (max_k + 1);
-    dim3 grid((n + 255) / 256, n_real);
-    hipLaunchKernelGGL(force_table_kernel, grid, dim3(256), 0, s, d_desc, d_step, step_off,
-                       fp32 ? 1 : 0);
+hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s) {
+    if (a.n_gitems <= 0) return hipSuccess;
+    const dim3 grid(a.n_gitems), block(kTileW, a.th);
+    if (fp32) hipLaunchKernelGGL(force_table_kernel<float>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(force_table_kernel<double>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@
 //   equilibrium coefficients ->  force field + projected force term  ->
 //   Anderson-Witting collision  ->  store.
 // Only the population loads and stores touch HBM.
+#include <hip/hip_ext.h>
+
 #include "site.hpp"
 
 #ifndef RLBM_STORAGE_ID
@@ -117,31 +119,32 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             T Fx = 0, Fy = 0;
             const int K = uni(Dsc.K);          // -1: this lattice is unforced (no table)
             if (K >= 0) {
-                const int yu = uni(y);     // one tile row per wavefront
-                const T* twp;
-                const T* gbase;
-                if constexpr (std::is_same<T, double>::value) {
-                    twp = uni(Dsc.tw64);
-                    gbase = uni(Dsc.g64);
-                } else {
-                    twp = uni(Dsc.tw32);
-                    gbase = uni(Dsc.g32);
-                }
-                const T c1 = ((gp<const T>)twp)[2 * x];
-                const T s1 = ((gp<const T>)twp)[2 * x + 1];
-                const gp<const T> grow = (gp<const T>)(gbase + (size_t)yu * (K + 1) * 4);
+                const int yu = uni(y);         // one tile row per wavefront
+                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
+                const T c1 = twx[2 * x];
+                const T s1 = twx[2 * x + 1];
+                const gp<const T> grow =
+                    (gp<const T>)uni((const T*)Dsc.g[par]) + (size_t)yu * (K + 1) * 4;
                 Fx = grow[0];
                 Fy = grow[2];
                 T cp = 1, sp = 0, ck = c1, sk = s1;
                 const T two_c1 = c1 + c1;
-                for (int k = 1; k <= K; ++k) {
-                    const gp<const T> gk = grow + 4 * k;
-                    Fx = fma(ck, gk[0], fma(-sk, gk[1], Fx));
-                    Fy = fma(ck, gk[2], fma(-sk, gk[3], Fy));
+                auto term = [&](T g0, T g1, T g2, T g3) {
+                    Fx = fma(ck, g0, fma(-sk, g1, Fx));
+                    Fy = fma(ck, g2, fma(-sk, g3, Fy));
                     const T cn = fma(two_c1, ck, -cp);
                     const T sn = fma(two_c1, sk, -sp);
                     cp = ck; sp = sk; ck = cn; sk = sn;
+                };
+                int k = 1;
+                for (; k + 3 <= K; k += 4) {      // four table rows per batch of loads
+                    T gv[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) gv[i] = grow[4 * k + i];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
                 }
+                for (; k <= K; ++k) term(grow[4 * k], grow[4 * k + 1], grow[4 * k + 2], grow[4 * k + 3]);
             }
             const T E = (T)E64;
             fa = (T)(-0.5) * dt * (Fx * m.Jx + Fy * m.Jy);
@@ -201,6 +204,15 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
         });
         (void)sig;
     }
+
+    // force table of the next step: items of this XCD, spread over its blocks
+    if constexpr (FORCED) {
+        for (int u = xcd + 8 * (b >> 3); u < A.n_gitems; u += 8 * nb) {
+            const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
+            const RealDesc& Dsc = A.desc[r];
+            force_item<T>(Dsc, u - uni(Dsc.gitem_begin), step + 1, kTileW * A.th);
+        }
+    }
 }
 
 template <class St, bool UNIT, bool FORCED>
@@ -235,6 +247,9 @@ hipError_t RLBM_LAUNCH_NAME(const StepLaunch& L) {
     const void* k = select_kernel(L.stencil, L.unit_cfl, L.forced);
     StepArgs a = L.args;
     void* params[] = {&a};
+    if (L.ev_start)
+        return hipExtLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, 0, L.stream,
+                                  L.ev_start, L.ev_stop, 0);
     return hipLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, 0, L.stream);
 }
 

@@ -69,10 +69,10 @@ struct StF64 {
     __device__ static double to64(raw v) { return v; }
     __device__ static raw from64(double v) { return v; }
 };
-struct StF32 {
+struct StF32 {            // stores F - 1 in FP32: the deviation keeps all 24 bits
     using raw = float;
     using T = float;
-    static constexpr int shift = 0;
+    static constexpr int shift = 1;
     static constexpr int id = RLBM_F32;
     template <class P> __device__ static T ld(P p) { return *p; }
     template <class P> __device__ static void st(P p, T v) { *p = v; }
@@ -260,6 +260,117 @@ __device__ __forceinline__ void eq_coeffs(double eps, double bx, double by, doub
     B = D * hp;
     C = (D * (D + 2) * 0.5) * hp;
     A0 = hp - eps * invD - C * b2 * invD;
+}
+
+}  // namespace rlbm
+
+namespace rlbm {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
+// 32x32->64-bit multiplies by fixed odd constants, high/low halves mixed with
+// the other two counter words and the key, key bumped by Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+        const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force table of one time step (paper Sec. V forcing, redrawn every step).
+// For row y and k = |kx| in [0, K]:
+//   G_kx(y) = sum over the modes with this kx of
+//             A r (cos th, sin th) exp(i phi) exp(i 2 pi ky y / ny),
+//   P_c(k, y) = Re G_k + Re G_-k,   Q_c(k, y) = Im G_k - Im G_-k,
+// so that F_c(x, y) = sum_k cos(2 pi k x/nx) P_c(k, y) - sin(2 pi k x/nx) Q_c(k, y).
+// Per mode, Philox4x32-10 with counter (m, step, realization, 0) and key
+// seed gives r = u(x0), th = 2 pi u(x1), phi = 2 pi u(x2), u(x) = (x + 1/2) 2^-32.
+//
+// One work item = one k and the 64*th rows [chunk * 64 th, ...), one row per
+// thread of the block.  The draws of up to 64 modes are computed once per
+// item by the first wavefront and shared through LDS; exp(i 2 pi ky y / ny)
+// comes from the row twiddle table.  Must be called by every thread of the
+// block (it synchronises).
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void force_item(const RealDesc& Dsc, int local_item, int64_t step, int rows) {
+    __shared__ T sm_c[64][4];
+    __shared__ int sm_ky[64];
+    __shared__ T sm_sg[64];
+    const int K1 = uni(Dsc.K) + 1;
+    const int ny = uni(Dsc.ny);
+    const int chunk = local_item / K1;
+    const int k = local_item - chunk * K1;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int y = chunk * rows + tid;
+    const gp<const T> twy = (gp<const T>)uni((const T*)Dsc.twy);
+    const gp<const int> modes = (gp<const int>)uni((const int*)Dsc.modes);   // (kx, ky, m, 0)
+    const gp<const int> kptr = (gp<const int>)uni(Dsc.kptr);
+    const int j0 = kptr[k], j1 = kptr[k + 1];
+    const uint64_t seed = uni(Dsc.seed);
+    const uint32_t real = (uint32_t)uni(Dsc.realization);
+    const double amp = uni(Dsc.amplitude);
+    T Px = 0, Qx = 0, Py = 0, Qy = 0;
+    for (int jb = j0; jb < j1; jb += 64) {
+        const int nm = min(64, j1 - jb);
+        if (tid < nm) {
+            const int mkx = modes[4 * (jb + tid)];
+            const int mky = modes[4 * (jb + tid) + 1];
+            const int mid = modes[4 * (jb + tid) + 2];
+            uint32_t c[4] = {(uint32_t)mid, (uint32_t)(uint64_t)step, real, 0u};
+            philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+            const double u32 = 2.3283064365386963e-10;   // 2^-32
+            const double two_pi = 2.0 * M_PI;
+            const double rmag = ((double)c[0] + 0.5) * u32;
+            const double th = two_pi * (((double)c[1] + 0.5) * u32);
+            const double ph = two_pi * (((double)c[2] + 0.5) * u32);
+            T ct, st, cph, sph;
+            if constexpr (std::is_same<T, double>::value) {
+                sincos(th, &st, &ct);
+                sincos(ph, &sph, &cph);
+            } else {
+                sincosf((float)th, &st, &ct);
+                sincosf((float)ph, &sph, &cph);
+            }
+            const T ax = (T)(amp * rmag) * ct, ay = (T)(amp * rmag) * st;
+            sm_c[tid][0] = ax * cph;
+            sm_c[tid][1] = ax * sph;
+            sm_c[tid][2] = ay * cph;
+            sm_c[tid][3] = ay * sph;
+            sm_ky[tid] = mky;
+            sm_sg[tid] = mkx < 0 ? (T)-1 : (T)1;
+        }
+        __syncthreads();
+        if (y < ny) {
+            for (int i = 0; i < nm; ++i) {
+                const int jy = (int)(((long long)sm_ky[i] * y) % ny);
+                const T cy = twy[2 * jy], sy = twy[2 * jy + 1];
+                // (a + i b) exp(i psi): real a cy - b sy, imaginary b cy + a sy
+                Px += fma(sm_c[i][0], cy, -sm_c[i][1] * sy);
+                Qx += sm_sg[i] * fma(sm_c[i][1], cy, sm_c[i][0] * sy);
+                Py += fma(sm_c[i][2], cy, -sm_c[i][3] * sy);
+                Qy += sm_sg[i] * fma(sm_c[i][3], cy, sm_c[i][2] * sy);
+            }
+        }
+        __syncthreads();
+    }
+    if (y < ny) {
+        const gp<T> g = (gp<T>)uni((T*)Dsc.g[(int)(step & 1)]);
+        const size_t o = ((size_t)y * K1 + k) * 4;
+        g[o + 0] = Px;
+        g[o + 1] = Qx;
+        g[o + 2] = Py;
+        g[o + 3] = Qy;
+    }
 }
 
 }  // namespace rlbm
