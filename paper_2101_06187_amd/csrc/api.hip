@@ -161,7 +161,7 @@ struct Engine {
     uint16_t* d_gitems = nullptr;
     int n_gitems = 0;
     bool unit_cfl = true, any_forced = false;
-    int th = 4, n_tiles = 0, grid = 0, cus = 0;
+    int th = 4, n_tiles = 0, grid = 0, cus = 0, tile_blocks = 0, extra_blocks = 0;
     int64_t step = 0;
     int graph_chunk = 0;
     int graph_built_chunk = 0;
@@ -216,7 +216,13 @@ struct Engine {
                                   hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
         const int per_cu = occupancy();
-        grid = std::max(8, std::min(n_tiles, cus * per_cu));
+        const int slots = cus * per_cu;
+        tile_blocks = std::max(8, std::min(n_tiles, slots));
+        // when the tiles leave resident slots free, build the next force table
+        // on extra blocks that run alongside the tiles
+        extra_blocks = 0;
+        if (any_forced && tile_blocks < slots) extra_blocks = std::min(n_gitems, slots - tile_blocks);
+        grid = tile_blocks + extra_blocks;
         drop_graph();
         return RLBM_OK;
     }
@@ -262,6 +268,7 @@ struct Engine {
         L.args.n_tiles = n_tiles;
         L.args.n_gitems = any_forced ? n_gitems : 0;
         L.args.th = th;
+        L.args.tile_blocks = tile_blocks;
         L.stencil = stencil;
         L.unit_cfl = unit_cfl;
         L.forced = any_forced;
@@ -431,7 +438,6 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         d.nx = lat.nx;
         d.ny = lat.ny;
         d.pitch = pitch_of(lat.nx);
-        d.plane = (long long)d.pitch * lat.ny;
         d.K = E.mts[r].n > 0 ? E.mts[r].K : -1;
         d.n_modes = E.mts[r].n;
         d.realization = r;
@@ -778,10 +784,10 @@ int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes) {
     const int s = storage_bytes(E.storage);
     const RealDesc& d = E.hdesc[0];
     char* dst = (char*)h_buf + sizeof(h);
-    for (int q = 0; q < E.Q; ++q)
+    for (int q = 0; q < E.Q; ++q)   // population q: rows (q + y Q) * pitch apart
         HIPCHK(hipMemcpy2DAsync(dst + (size_t)q * d.nx * d.ny * s, (size_t)d.nx * s,
-                                (const char*)d.buf[E.parity()] + (size_t)q * d.plane * s,
-                                (size_t)d.pitch * s, (size_t)d.nx * s, d.ny,
+                                (const char*)d.buf[E.parity()] + (size_t)q * d.pitch * s,
+                                (size_t)d.pitch * E.Q * s, (size_t)d.nx * s, d.ny,
                                 hipMemcpyDeviceToHost, E.stream));
     HIPCHK(hipStreamSynchronize(E.stream));
     return RLBM_OK;
@@ -807,8 +813,8 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
     const RealDesc& d = E.hdesc[0];
     const char* src = (const char*)h_buf + sizeof(h);
     for (int q = 0; q < E.Q; ++q)
-        HIPCHK(hipMemcpy2DAsync((char*)d.buf[E.parity()] + (size_t)q * d.plane * s,
-                                (size_t)d.pitch * s, src + (size_t)q * d.nx * d.ny * s,
+        HIPCHK(hipMemcpy2DAsync((char*)d.buf[E.parity()] + (size_t)q * d.pitch * s,
+                                (size_t)d.pitch * E.Q * s, src + (size_t)q * d.nx * d.ny * s,
                                 (size_t)d.nx * s, (size_t)d.nx * s, d.ny, hipMemcpyHostToDevice,
                                 E.stream));
     if (int rc = E.prime_force_table()) return rc;

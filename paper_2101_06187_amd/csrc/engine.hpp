@@ -24,8 +24,9 @@ struct RealDesc {
                                   //   [ny][K+1][4] = Px, Qx, Py, Qy (compute type)
     const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
     const int* kptr;              // K+2 offsets into modes
-    long long plane;              // elements per population plane (pitch * ny)
-    int nx, ny, pitch;
+    int nx, ny;
+    int pitch;                    // elements per population row; element (q, y, x)
+                                  // is at (y * Q + q) * pitch + x (row-interleaved)
     int tiles_x, tiles_y;
     int tile_begin;               // first tile of this lattice in the launch
     int K;                        // largest |kx| of the driven modes; -1 unforced
@@ -55,6 +56,8 @@ struct StepArgs {
     int n_tiles;
     int n_gitems;                 // force-table items of the next step (0: unforced)
     int th;                       // tile height (rows of 64 sites)
+    int tile_blocks;              // blocks [0, tile_blocks) walk the tiles; any further
+                                  // blocks only build the next force table
 };
 
 struct StepLaunch {

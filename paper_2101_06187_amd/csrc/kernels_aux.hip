@@ -71,7 +71,7 @@ __global__ void set_state_kernel(const RealDesc* desc, int r, const double* e,
         constexpr double vx = dir_comp(St::dir[q], 0), vy = dir_comp(St::dir[q], 1);
         const double t = vx * bx + vy * by;
         const double F = fma(C, t * t, fma(B, t, A0));
-        dst[(long long)q * D.plane + (long long)y * D.pitch + x] = S::from64(F - S::shift);
+        dst[((long long)y * St::Q + q) * D.pitch + x] = S::from64(F - S::shift);
     });
 }
 
@@ -83,7 +83,7 @@ __global__ void set_pop_kernel(const RealDesc* desc, int r, const double* in, in
     if (x >= D.nx) return;
     typename S::raw* dst = (typename S::raw*)D.buf[parity];
     for (int q = 0; q < St::Q; ++q)
-        dst[(long long)q * D.plane + (long long)y * D.pitch + x] =
+        dst[((long long)y * St::Q + q) * D.pitch + x] =
             S::from64(in[((long long)q * D.ny + y) * D.nx + x] - S::shift);
 }
 
@@ -96,7 +96,7 @@ __global__ void get_pop_kernel(const RealDesc* desc, int r, double* out, int par
     const typename S::raw* src = (const typename S::raw*)D.buf[parity];
     for (int q = 0; q < St::Q; ++q)
         out[((long long)q * D.ny + y) * D.nx + x] =
-            S::to64(src[(long long)q * D.plane + (long long)y * D.pitch + x]) + S::shift;
+            S::to64(src[((long long)y * St::Q + q) * D.pitch + x]) + S::shift;
 }
 
 // ---------------------------------------------------------------------------
@@ -110,19 +110,20 @@ __global__ void fields_kernel(const RealDesc* desc, int r, int parity, double* e
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= D.nx) return;
-    const int nx = D.nx, ny = D.ny, pitch = D.pitch;
+    const int nx = D.nx, ny = D.ny;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const int rows[3] = {ym * pitch, y * pitch, yp * pitch};
-    const int cols[3] = {xm, x, xp};
-    uint32_t off[3][3];
-    for (int j = 0; j < 3; ++j)
-        for (int i = 0; i < 3; ++i)
-            off[j][i] = (uint32_t)(rows[j] + cols[i]) * sizeof(typename S::raw);
+    const long long plane_bytes = (long long)D.pitch * sizeof(typename S::raw);
+    const long long rowq = plane_bytes * St::Q;
+    const char* src = (const char*)uni(D.buf[parity]);
+    const char* const rows[3] = {src + ym * rowq, src + y * rowq, src + yp * rowq};
+    const uint32_t cols[3] = {(uint32_t)(xm * sizeof(typename S::raw)),
+                              (uint32_t)(x * sizeof(typename S::raw)),
+                              (uint32_t)(xp * sizeof(typename S::raw))};
+    InterpW<double> W;
+    W.set(D.a[0], D.a[1], D.a[2]);
     double f[St::Q];
-    stream_pull<S, St, UNIT, double>((const char*)D.buf[parity],
-                                     D.plane * (long long)sizeof(typename S::raw), off,
-                                     D.a[0], D.a[1], D.a[2], f);
+    stream_pull<S, St, UNIT, double>(rows, plane_bytes, cols, W, f);
     const Moments<double> m = moments<St, false>(f);
     const double sh = (double)S::shift;
     const double E = m.E + sh, Pxx = m.Pxx + sh / St::D, Pyy = m.Pyy + sh / St::D;
@@ -190,7 +191,7 @@ conserved_kernel(const RealDesc* desc, int r, int parity, double* partials) {
         const int y = (int)(i / D.nx), x = (int)(i - (long long)y * D.nx);
         double f[St::Q];
         for (int q = 0; q < St::Q; ++q)
-            f[q] = S::to64(src[(long long)q * D.plane + (long long)y * D.pitch + x]);
+            f[q] = S::to64(src[((long long)y * St::Q + q) * D.pitch + x]);
         const Moments<double> m = moments<St, false>(f);
         acc[0] += m.E + (double)S::shift;
         acc[1] += m.Jx;

@@ -102,16 +102,38 @@ struct StBF16S {
 
 // ---------------------------------------------------------------------------
 // pull streaming by linear interpolation (Sec. III B), periodic lattice.
-// off[j][i] is the byte offset of node (x + i - 1, y + j - 1) within a plane.
+// Populations are stored row-interleaved: element (q, y, x) at
+// (y * Q + q) * pitch + x, so one lattice row of every population is one
+// contiguous block of memory.
+// rows[j] is the (wave-uniform) address of lattice row y + j - 1, cols[i] the
+// per-lane byte offset of column x + i - 1, plane_bytes = pitch * sizeof(raw).
 // The population of direction c arriving at x comes from x - cfl * v: for
-// c_x > 0 it lies between x - 1 (weight a) and x (weight 1 - a), a = cfl |v_x|.
+// c_x > 0 it lies between x - 1 (weight a) and x (weight 1 - a), a = cfl |v_x|;
+// for c_x, c_y both non-zero (|v_x| = |v_y|) the bilinear weights are
+// (1 - a)^2 (own node), a (1 - a) (each edge neighbour), a^2 (diagonal).
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ T lerp(T p, T q, T t) { return fma(t, q - p, p); }
 
+template <class T>
+struct InterpW {
+    T a[3];       // cfl |v| for 1, 2, 3 non-zero cube components
+    T w00[3], w10[3], w11[3];
+    __device__ void set(T a1, T a2, T a3) {
+        a[0] = a1; a[1] = a2; a[2] = a3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T b = (T)1 - a[i];
+            w00[i] = b * b;
+            w10[i] = a[i] * b;
+            w11[i] = a[i] * a[i];
+        }
+    }
+};
+
 template <class S, class St, bool UNIT, class T>
-__device__ __forceinline__ void stream_pull(const char* base, long long plane_bytes,
-                                            const uint32_t (&off)[3][3], T a1, T a2, T a3,
+__device__ __forceinline__ void stream_pull(const char* const (&rows)[3], long long plane_bytes,
+                                            const uint32_t (&cols)[3], const InterpW<T>& W,
                                             T (&f)[St::Q]) {
     using raw = typename S::raw;
     sfor<0, St::Q>([&](auto iq) {
@@ -120,21 +142,20 @@ __device__ __forceinline__ void stream_pull(const char* base, long long plane_by
         constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
         constexpr int ux = d.cx > 0 ? 0 : (d.cx < 0 ? 2 : 1);   // upstream column index
         constexpr int uy = d.cy > 0 ? 0 : (d.cy < 0 ? 2 : 1);   // upstream row index
-        const gp<const char> pq = (gp<const char>)(base + (long long)q * plane_bytes);
-        auto L = [&](int j, int i) -> T { return (T)S::ld((gp<const raw>)(pq + off[j][i])); };
-        const T a = n == 1 ? a1 : (n == 2 ? a2 : a3);
+        auto L = [&](int j, int i) -> T {
+            return (T)S::ld((gp<const raw>)(rows[j] + (long long)q * plane_bytes + cols[i]));
+        };
         if constexpr (d.cx == 0 && d.cy == 0) {
             f[q] = L(1, 1);
         } else if constexpr (d.cy == 0) {
             if constexpr (UNIT && n == 1) f[q] = L(1, ux);
-            else f[q] = lerp(L(1, 1), L(1, ux), a);
+            else f[q] = lerp(L(1, 1), L(1, ux), W.a[n - 1]);
         } else if constexpr (d.cx == 0) {
             if constexpr (UNIT && n == 1) f[q] = L(uy, 1);
-            else f[q] = lerp(L(1, 1), L(uy, 1), a);
+            else f[q] = lerp(L(1, 1), L(uy, 1), W.a[n - 1]);
         } else {
-            const T p0 = lerp(L(1, 1), L(1, ux), a);
-            const T p1 = lerp(L(uy, 1), L(uy, ux), a);
-            f[q] = lerp(p0, p1, a);
+            const T s = L(1, ux) + L(uy, 1);
+            f[q] = fma(W.w11[n - 1], L(uy, ux), fma(W.w10[n - 1], s, W.w00[n - 1] * L(1, 1)));
         }
     });
 }
@@ -202,8 +223,7 @@ __device__ __forceinline__ double rcp64(double x) {
 
 __device__ __forceinline__ double rsqrt64(double x) {
     double y = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
+    const double h = 0.5 * x;
     y = y * fma(-h * y, y, 1.5);
     return y * fma(-h * y, y, 1.5);
 }
@@ -222,23 +242,20 @@ __device__ __forceinline__ bool landau64(double E, double Jx, double Jy, double 
                                          double Pxy, double Pyy, double& eps, double& bx,
                                          double& by) {
     const double J2 = Jx * Jx + Jy * Jy;
+    const double Pxy2 = Pxy * Pxy;
     double e = E - J2 * ((double)D / (D + 1)) * rcp64(E);
     bool ok = false;
     for (int it = 0; it < 16; ++it) {
         const double a = e + Pxx, c = e + Pyy;
-        const double inv = rcp64(fma(a, c, -Pxy * Pxy));
+        const double inv = rcp64(fma(a, c, -Pxy2));
         bx = (c * Jx - Pxy * Jy) * inv;
         by = (a * Jy - Pxy * Jx) * inv;
         const double g = e - E + Jx * bx + Jy * by;
-        const double gp = 1.0 - bx * bx - by * by;
-        const double de = g * rcp64(gp);
+        const double de = g * rcp64(1.0 - bx * bx - by * by);
         e -= de;
+        // converged: beta of this pass belongs to eps to within |de| ~ 1 ulp
         if (!(fabs(de) > 4e-16 * fabs(e))) { ok = true; break; }
     }
-    const double a = e + Pxx, c = e + Pyy;
-    const double inv = rcp64(fma(a, c, -Pxy * Pxy));
-    bx = (c * Jx - Pxy * Jy) * inv;
-    by = (a * Jy - Pxy * Jx) * inv;
     eps = e;
     const double b2 = bx * bx + by * by;
     return ok && e > 0.0 && b2 < 1.0 && isfinite(e) && isfinite(b2);
@@ -253,8 +270,8 @@ template <int D>
 __device__ __forceinline__ void eq_coeffs(double eps, double bx, double by, double& A0,
                                           double& B, double& C, double& gamma) {
     const double b2 = bx * bx + by * by;
-    const double g2 = rcp64(1.0 - b2);
     gamma = rsqrt64(1.0 - b2);
+    const double g2 = gamma * gamma;
     constexpr double invD = 1.0 / D;
     const double hp = eps * ((D + 1.0) / D) * g2;     // (eps + P) gamma^2
     B = D * hp;
@@ -353,7 +370,16 @@ __device__ void force_item(const RealDesc& Dsc, int local_item, int64_t step, in
         if (y < ny) {
             for (int i = 0; i < nm; ++i) {
                 const int jy = (int)(((long long)sm_ky[i] * y) % ny);
-                const T cy = twy[2 * jy], sy = twy[2 * jy + 1];
+                T cy, sy;
+                if constexpr (std::is_same<T, double>::value) {
+                    cy = twy[2 * jy];
+                    sy = twy[2 * jy + 1];
+                } else {
+                    // hardware sine/cosine take the angle in revolutions
+                    const float rev = (float)jy / (float)ny;
+                    cy = __builtin_amdgcn_cosf(rev);
+                    sy = __builtin_amdgcn_sinf(rev);
+                }
                 // (a + i b) exp(i psi): real a cy - b sy, imaginary b cy + a sy
                 Px += fma(sm_c[i][0], cy, -sm_c[i][1] * sy);
                 Qx += sm_sg[i] * fma(sm_c[i][1], cy, sm_c[i][0] * sy);
