@@ -116,7 +116,39 @@ def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n):
         "steps_done": warmup + steps + prof_n,
     }
     out["kernel_frac_hbm_peak"] = out["kernel_gbs"] / HBM_PEAK_GBS
+    out["kernel_form"] = list(lat.kernel())
     return lat, out
+
+
+def run_ensemble(rl, torch, steps, warmup, chunk=20):
+    """The 256-lattice ensemble (sides from {64, 128, 256}, tau in [0.51, 0.8]),
+    FP32 populations, one persistent launch per step, graph replay."""
+    import workloads
+    spec = workloads.ensemble()
+    sizes = [(n, n) for n, _ in spec]
+    taus = [t for _, t in spec]
+    frs = [rl.Forcing(1e-5, 2.0, 4.0, r) for r in range(len(spec))]
+    ens = rl.Ensemble(sizes, taus, storage="F32", forcings=frs)
+    for r, (n, _) in enumerate(spec):
+        e, bx, by = workloads.noisy_rest(n, n, 0.005, seed=r)
+        ens.set_state(r, *(torch.from_numpy(a).to("cuda:0") for a in (e, bx, by)))
+    ens.set_graph_chunk(chunk)
+    ens.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    ens.step(steps)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    sites = sum(n * n for n, _ in spec)
+    out = {"realizations": len(spec), "sites": sites, "ms_per_step": ms,
+           "mlups": sites / (ms * 1e-3) / 1e6,
+           "step_gbs": 2 * Q * BYTES["F32"] * sites / (ms * 1e-3) / 1e9,
+           "unstable": ens.check() != rl.OK}
+    ens.close()
+    return out
 
 
 def cpu_baseline(wl, n_steps):
@@ -222,9 +254,15 @@ def main():
                 torch.cuda.empty_cache()
                 extra[name][storage] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms",
                                                           "kernel_gbs", "kernel_frac_hbm_peak",
-                                                          "unstable")}
+                                                          "unstable", "kernel_form")}
                 log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
                     f"({100 * r['kernel_frac_hbm_peak']:.1f}% of HBM peak)")
+
+    if not a.no_extra:
+        extra["ensemble256"] = run_ensemble(rl, torch, 200, 20)
+        torch.cuda.empty_cache()
+        log(f"ensemble256 F32: {extra['ensemble256']['mlups']:.0f} MLUPS, "
+            f"{extra['ensemble256']['step_gbs']:.0f} GB/s per step")
 
     head = forms["F32"]
     sites = wl.n * wl.n
@@ -233,7 +271,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["kernel_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,
-                "kernel": "rlbm::step_kernel<StF32, Sph26, unit cfl, forced>",
+                "kernel": ("rlbm::%s_kernel<StF32, Sph26, unit cfl, forced>"
+                           % ("march" if head["kernel_form"][0] == "march" else "step")),
                 "algorithmic_bytes_per_launch": per_launch,
                 "kernel_ms": head["kernel_ms"]}
 

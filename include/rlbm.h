@@ -185,10 +185,23 @@ int rlbm_state_bytes(const rlbm_ctx* ctx, size_t* h_bytes);
 int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes);
 int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
 
-/* Launch shape: tile height th in {1, 2, 4, 8} rows of 64 sites per block.
- * Results do not depend on it (bitwise).  rlbm_autotune times every tile
- * height for `steps` steps (advancing the state) and keeps the fastest;
- * *h_th receives it.                                                       */
+/* Kernel form and launch shape.  Results never depend on them (bitwise).
+ *   RLBM_KERNEL_TILE  -- every thread streams one site from global memory;
+ *                        param = tile height th in {1, 2, 4, 8} rows of 64 sites.
+ *   RLBM_KERNEL_MARCH -- each wavefront marches down a 64-column strip, loading
+ *                        every population row once into a rolling register
+ *                        window; param = rows per strip segment (0: chosen
+ *                        from the lattice size and the GPU's resident waves).
+ * By default the library picks RLBM_KERNEL_MARCH (param 0) for FP32 storage
+ * when every resident wavefront gets a segment of at least 8 rows, and
+ * RLBM_KERNEL_TILE with th = 4 otherwise.  rlbm_set_tile(th) is
+ * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_autotune times the tile
+ * heights and two segment lengths for `steps` steps each (advancing the
+ * state) and keeps the fastest; *h_th receives th, or minus the segment
+ * length for the marching form.                                            */
+enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1 };
+int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param);
+int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param);
 int rlbm_set_tile(rlbm_ctx* ctx, int32_t th);
 int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th);
 

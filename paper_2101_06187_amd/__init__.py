@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
 STENCILS = {"SPH26": 0, "CIRC8": 1}
 STORAGES = {"F64": 0, "F32": 1, "F16S": 2, "BF16S": 3}
+KERNELS = {"tile": 0, "march": 1}
 
 OK, EINVAL, ENOSPACE, EHIP, EUNSTABLE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 
@@ -82,6 +83,8 @@ SIGNATURES = [
     ("rlbm_state_bytes", _I, [_P, _P]),
     ("rlbm_save", _I, [_P, _P, _SZ]),
     ("rlbm_load", _I, [_P, _P, _SZ]),
+    ("rlbm_set_kernel", _I, [_P, _I32, _I32]),
+    ("rlbm_get_kernel", _I, [_P, _P, _P]),
     ("rlbm_set_tile", _I, [_P, _I32]),
     ("rlbm_autotune", _I, [_P, _I32, _P]),
     ("rlbm_set_graph_chunk", _I, [_P, _I32]),
@@ -263,6 +266,16 @@ class Lattice:
 
     def set_tile(self, th):
         _check(lib().rlbm_set_tile(self._ctx, int(th)))
+
+    def set_kernel(self, kind, param=0):
+        """kind "tile" (param = tile height 1/2/4/8) or "march" (param = rows
+        per strip segment, 0 = automatic)."""
+        _check(lib().rlbm_set_kernel(self._ctx, KERNELS[kind], int(param)))
+
+    def kernel(self):
+        k, p = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rlbm_get_kernel(self._ctx, ctypes.byref(k), ctypes.byref(p)))
+        return ("tile" if k.value == KERNELS["tile"] else "march"), p.value
 
     def autotune(self, steps=20):
         th = ctypes.c_int32()

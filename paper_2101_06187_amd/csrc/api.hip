@@ -162,6 +162,8 @@ struct Engine {
     int n_gitems = 0;
     bool unit_cfl = true, any_forced = false;
     int th = 4, n_tiles = 0, grid = 0, cus = 0, tile_blocks = 0, extra_blocks = 0;
+    int kind = kKernelTile, seglen_req = 0, seglen = 0;
+    bool kind_auto = true;         // until rlbm_set_kernel / rlbm_set_tile / autotune
     int64_t step = 0;
     int graph_chunk = 0;
     int graph_built_chunk = 0;
@@ -181,15 +183,45 @@ struct Engine {
 
     int occupancy() const {
         switch (storage) {
-            case RLBM_F64: return occ_f64(stencil, unit_cfl, any_forced, th);
-            case RLBM_F32: return occ_f32(stencil, unit_cfl, any_forced, th);
-            case RLBM_F16S: return occ_f16s(stencil, unit_cfl, any_forced, th);
-            default: return occ_bf16s(stencil, unit_cfl, any_forced, th);
+            case RLBM_F64: return occ_f64(kind, stencil, unit_cfl, any_forced, th);
+            case RLBM_F32: return occ_f32(kind, stencil, unit_cfl, any_forced, th);
+            case RLBM_F16S: return occ_f16s(kind, stencil, unit_cfl, any_forced, th);
+            default: return occ_bf16s(kind, stencil, unit_cfl, any_forced, th);
         }
     }
 
-    // tiles of height th, tile map, persistent grid
+    // work items (tiles of 64 x th sites, or strip segments of 64 columns x
+    // seglen rows for the marching kernel), their maps, the persistent grid
+    // Default form (measured on MI355X): the row-marching kernel when every
+    // wavefront gets a strip segment of at least 8 rows with FP32 storage; the
+    // tile kernel otherwise (small lattices, FP64, 16-bit storage).
+    void choose_kind() {
+        if (!kind_auto) return;
+        long long wave_rows = 0;
+        for (int r = 0; r < n_real; ++r)
+            wave_rows += (long long)((hdesc[r].nx + kTileW - 1) / kTileW) * hdesc[r].ny;
+        kind = kKernelMarch;
+        th = 4;
+        const long long waves = (long long)cus * occupancy() * 4;
+        const bool long_segments = wave_rows >= 8 * std::max(1LL, waves);
+        kind = (storage == RLBM_F32 && long_segments) ? kKernelMarch : kKernelTile;
+    }
+
     int configure_tiles() {
+        choose_kind();
+        if (kind == kKernelMarch) th = 4;             // 4 wavefronts per block
+        const int per_cu = occupancy();
+        const int slots = cus * per_cu;
+        int seg = seglen_req;
+        if (kind == kKernelMarch && seg <= 0) {
+            // about one strip segment per resident wavefront, at least 2 rows
+            long long wave_rows = 0;
+            for (int r = 0; r < n_real; ++r)
+                wave_rows += (long long)((hdesc[r].nx + kTileW - 1) / kTileW) * hdesc[r].ny;
+            const long long target = std::max(1LL, (long long)slots * 4);
+            seg = (int)std::max(2LL, (wave_rows + target - 1) / target);
+        }
+        seglen = seg;
         n_tiles = 0;
         n_gitems = 0;
         std::vector<uint16_t> map, gmap;
@@ -197,7 +229,8 @@ struct Engine {
         for (int r = 0; r < n_real; ++r) {
             RealDesc& d = hdesc[r];
             d.tiles_x = (d.nx + kTileW - 1) / kTileW;
-            d.tiles_y = (d.ny + th - 1) / th;
+            d.seglen = kind == kKernelMarch ? seg : th;
+            d.tiles_y = (d.ny + d.seglen - 1) / d.seglen;
             d.tile_begin = n_tiles;
             n_tiles += d.tiles_x * d.tiles_y;
             if (n_real > 1) map.insert(map.end(), (size_t)d.tiles_x * d.tiles_y, (uint16_t)r);
@@ -215,9 +248,8 @@ struct Engine {
             HIPCHK(hipMemcpyAsync(d_gitems, gmap.data(), sizeof(uint16_t) * gmap.size(),
                                   hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        const int per_cu = occupancy();
-        const int slots = cus * per_cu;
-        tile_blocks = std::max(8, std::min(n_tiles, slots));
+        const int groups = kind == kKernelMarch ? (n_tiles + 3) / 4 : n_tiles;
+        tile_blocks = std::max(8, std::min(groups, slots));
         // when the tiles leave resident slots free, build the next force table
         // on extra blocks that run alongside the tiles
         extra_blocks = 0;
@@ -259,6 +291,7 @@ struct Engine {
 
     StepLaunch make_launch(int step_off, hipStream_t s) const {
         StepLaunch L;
+        L.kind = kind;
         L.args.desc = d_desc;
         L.args.tile_real = n_real > 1 ? d_tiles : nullptr;
         L.args.gitem_real = n_real > 1 ? d_gitems : nullptr;
@@ -825,8 +858,37 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
 int rlbm_set_tile(rlbm_ctx* ctx, int32_t th) {
     if (int rc = check_ctx(ctx)) return rc;
     if (th != 1 && th != 2 && th != 4 && th != 8) return fail(RLBM_EINVAL, "tile height must be 1, 2, 4 or 8");
+    ctx->e.kind = kKernelTile;
+    ctx->e.kind_auto = false;
     ctx->e.th = th;
     return ctx->e.configure_tiles();
+}
+
+int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param) {
+    if (int rc = check_ctx(ctx)) return rc;
+    Engine& E = ctx->e;
+    E.kind_auto = false;
+    if (kind == RLBM_KERNEL_TILE) {
+        if (param != 1 && param != 2 && param != 4 && param != 8)
+            return fail(RLBM_EINVAL, "tile height must be 1, 2, 4 or 8");
+        E.kind = kKernelTile;
+        E.th = param;
+    } else if (kind == RLBM_KERNEL_MARCH) {
+        if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
+        E.kind = kKernelMarch;
+        E.seglen_req = param;
+    } else {
+        return fail(RLBM_EINVAL, "unknown kernel kind");
+    }
+    return E.configure_tiles();
+}
+
+int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param) {
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!h_kind || !h_param) return fail(RLBM_EINVAL, "NULL output");
+    *h_kind = ctx->e.kind == kKernelMarch ? RLBM_KERNEL_MARCH : RLBM_KERNEL_TILE;
+    *h_param = ctx->e.kind == kKernelMarch ? ctx->e.seglen : ctx->e.th;
+    return RLBM_OK;
 }
 
 int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
@@ -836,11 +898,15 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    E.kind_auto = false;
     float best = 1e30f;
-    int best_th = E.th;
-    const int cand[4] = {1, 2, 4, 8};
-    for (int th : cand) {
-        E.th = th;
+    int best_kind = E.kind, best_param = E.kind == kKernelMarch ? E.seglen_req : E.th;
+    const int cand[6][2] = {{kKernelTile, 1}, {kKernelTile, 2}, {kKernelTile, 4}, {kKernelTile, 8},
+                            {kKernelMarch, 0}, {kKernelMarch, -1}};
+    for (const auto& c : cand) {
+        E.kind = c[0];
+        if (c[0] == kKernelTile) E.th = c[1];
+        else E.seglen_req = c[1] == 0 ? 0 : std::max(2, 2 * E.seglen);   // auto, then twice as long
         if (int rc = E.configure_tiles()) return rc;
         if (int rc = E.run(1)) return rc;
         HIPCHK(hipEventRecord(e0, E.stream));
@@ -849,12 +915,18 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; best_th = th; }
+        if (ms < best) {
+            best = ms;
+            best_kind = E.kind;
+            best_param = E.kind == kKernelMarch ? E.seglen : E.th;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    E.th = best_th;
-    if (h_th) *h_th = best_th;
+    E.kind = best_kind;
+    if (best_kind == kKernelTile) E.th = best_param;
+    else E.seglen_req = best_param;
+    if (h_th) *h_th = best_kind == kKernelMarch ? -best_param : best_param;
     return E.configure_tiles();
 }
 

@@ -28,7 +28,8 @@ struct RealDesc {
     int pitch;                    // elements per population row; element (q, y, x)
                                   // is at (y * Q + q) * pitch + x (row-interleaved)
     int tiles_x, tiles_y;
-    int tile_begin;               // first tile of this lattice in the launch
+    int tile_begin;               // first work item (tile or strip segment) of this lattice
+    int seglen;                   // rows per strip segment (marching kernel)
     int K;                        // largest |kx| of the driven modes; -1 unforced
     int n_modes;
     int realization;              // Philox counter word 2
@@ -60,8 +61,11 @@ struct StepArgs {
                                   // blocks only build the next force table
 };
 
+enum { kKernelTile = 0, kKernelMarch = 1 };
+
 struct StepLaunch {
     StepArgs args;
+    int kind;                     // kKernelTile or kKernelMarch
     int stencil;
     bool unit_cfl;
     bool forced;
@@ -77,10 +81,10 @@ hipError_t launch_step_f32(const StepLaunch& L);
 hipError_t launch_step_f16s(const StepLaunch& L);
 hipError_t launch_step_bf16s(const StepLaunch& L);
 // Resident blocks per CU of a step-kernel configuration (occupancy query).
-int occ_f64(int stencil, bool unit_cfl, bool forced, int th);
-int occ_f32(int stencil, bool unit_cfl, bool forced, int th);
-int occ_f16s(int stencil, bool unit_cfl, bool forced, int th);
-int occ_bf16s(int stencil, bool unit_cfl, bool forced, int th);
+int occ_f64(int kind, int stencil, bool unit_cfl, bool forced, int th);
+int occ_f32(int kind, int stencil, bool unit_cfl, bool forced, int th);
+int occ_f16s(int kind, int stencil, bool unit_cfl, bool forced, int th);
+int occ_bf16s(int kind, int stencil, bool unit_cfl, bool forced, int th);
 
 // Force table of the current step (kernels_aux.hip), for initial states.
 hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s);

@@ -126,121 +126,17 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
         T f[St::Q];
         stream_pull<S, St, UNIT>(rows, plane_bytes, cols, W, f);
 
-        // (c) moments, Landau frame in FP64
-        const Moments<T> m = moments<St, FORCED>(f);
-        const double E64 = (double)m.E + (double)S::shift;
-        const double dshift = (double)S::shift / D;     // sum_q w v_i v_i = 1/D per axis
-        double eps, bx64, by64;
-        const bool ok = landau64<D>(E64, (double)m.Jx, (double)m.Jy,
-                                    (double)m.Pxx + dshift, (double)m.Pxy,
-                                    (double)m.Pyy + dshift, eps, bx64, by64);
-        if (!ok) *A.d_flag = 1;
-
-        // (d) equilibrium F_eq - shift = A0' + B t + C t^2 (t = beta.v), and the
-        // Anderson-Witting rate omega = g (1 - t), g = gamma / tau.  For the +v
-        // and -v members of a class:
-        //   omega (F_eq - shift) = E(t) +- O(t),
-        //   E = g A0' + g (C - B) t^2,   O = g (B - A0') t - g C t^3.
-        double A0d, Bd, Cd, gam;
-        eq_coeffs<D>(eps, bx64, by64, A0d, Bd, Cd, gam);
-        const double A0s = A0d - (double)S::shift;
-        const double g64 = gam * (double)ginv;
-        const T g = (T)g64;
-        const T k0 = (T)(g64 * A0s), k1 = (T)(g64 * (Bd - A0s));
-        const T k2 = (T)(g64 * (Cd - Bd)), k3 = (T)(g64 * Cd);
-        const T omg = (T)(1.0 - g64);
-        const T bx = (T)bx64, by = (T)by64;
-
-        // force term: dF(v) = a + b.v + v.M.v (Sec. III C, App. B)
-        T fa = 0, fbx = 0, fby = 0, Mxx = 0, Mxy = 0, Myy = 0, Mzz = 0;
+        const SiteCtx<T> sctx{ginv, dt, K, gtab, plane_bytes};
+        T c1 = 0, s1 = 0;
         if constexpr (FORCED) {
-            // F_c(x, y) = sum_k cos(k a) P_c(k, y) - sin(k a) Q_c(k, y), a = 2 pi x / nx;
-            // cos/sin(k a) by the Chebyshev recurrence.
-            T Fx = 0, Fy = 0;
-            if (K >= 0) {                       // K < 0: this lattice is unforced
+            if (K >= 0) {
                 const gp<const T> twx = (gp<const T>)twp;
-                const T c1 = twx[2 * x];
-                const T s1 = twx[2 * x + 1];
-                const gp<const T> grow = (gp<const T>)gtab + (size_t)y * (K + 1) * 4;
-                Fx = grow[0];
-                Fy = grow[2];
-                T cp = 1, sp = 0, ck = c1, sk = s1;
-                const T two_c1 = c1 + c1;
-                auto term = [&](T g0, T g1, T g2, T g3) {
-                    Fx = fma(ck, g0, fma(-sk, g1, Fx));
-                    Fy = fma(ck, g2, fma(-sk, g3, Fy));
-                    const T cn = fma(two_c1, ck, -cp);
-                    const T sn = fma(two_c1, sk, -sp);
-                    cp = ck; sp = sk; ck = cn; sk = sn;
-                };
-                int k = 1;
-                for (; k + 3 <= K; k += 4) {      // four table rows per batch of loads
-                    T gv[16];
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) gv[i] = grow[4 * k + i];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
-                }
-                for (; k <= K; ++k) term(grow[4 * k], grow[4 * k + 1], grow[4 * k + 2], grow[4 * k + 3]);
-            }
-            const T E = (T)E64;
-            fa = (T)(-0.5) * dt * (Fx * m.Jx + Fy * m.Jy);
-            fbx = dt * E * Fx;
-            fby = dt * E * Fy;
-            const T Sxx = Fx * m.Rxxx + Fy * m.Rxxy;
-            const T Sxy = Fx * m.Rxxy + Fy * m.Rxyy;
-            const T Syy = Fx * m.Rxyy + Fy * m.Ryyy;
-            const T k2f = (D == 3 ? (T)2.5 : (T)2.0) * dt;
-            Mxx = k2f * ((T)2 * Fx * m.Jx - Sxx);
-            Mxy = k2f * (Fx * m.Jy + Fy * m.Jx - Sxy);
-            Myy = k2f * ((T)2 * Fy * m.Jy - Syy);
-            if constexpr (D == 3) {
-                const T Rxzz = m.Jx - m.Rxxx - m.Rxyy;   // |v| = 1
-                const T Ryzz = m.Jy - m.Rxxy - m.Ryyy;
-                Mzz = -k2f * (Fx * Rxzz + Fy * Ryzz);
+                c1 = twx[2 * x];
+                s1 = twx[2 * x + 1];
             }
         }
-
-        // (e) collide + force, store:  F' <- (1 - omega) F' + omega (F_eq - shift) + dF
-        const gp<char> drow = (gp<char>)(dst + y * rowq_bytes);
-        const uint32_t own = cols[1];
-        sfor<0, St::NC>([&](auto ic) {
-            constexpr DirClass Cl = St::cls[ic];
-            constexpr double um = comp_mag(Cl.ncomp);
-            constexpr double ux = Cl.sx * um, uy = Cl.sy * um;
-            T t = 0;
-            if constexpr (ux != 0.0) t = (T)ux * bx;
-            if constexpr (uy != 0.0) t = fma((T)uy, by, t);
-            const T t2 = t * t;
-            const T Ev = fma(k2, t2, k0);
-            const T Ov = t * fma(-k3, t2, k1);
-            T dfe = fa, dfo = 0;
-            if constexpr (FORCED) {
-                if constexpr (ux != 0.0) dfe = fma((T)(ux * ux), Mxx, dfe);
-                if constexpr (ux != 0.0 && uy != 0.0) dfe = fma((T)(2.0 * ux * uy), Mxy, dfe);
-                if constexpr (uy != 0.0) dfe = fma((T)(uy * uy), Myy, dfe);
-                if constexpr (Cl.vz2 != 0.0) dfe = fma((T)Cl.vz2, Mzz, dfe);
-                if constexpr (ux != 0.0) dfo = (T)ux * fbx;
-                if constexpr (uy != 0.0) dfo = fma((T)uy, fby, dfo);
-            }
-            const T ep = Ev + dfe;
-            const T op = Ov + dfo;
-            const T gt = g * t;
-            const T Kp = ep + op;
-            const T mp = omg + gt;
-            sfor<0, Cl.nplus>([&](auto i) {
-                constexpr int q = Cl.first + decltype(i)::value;
-                S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), fma(mp, f[q], Kp));
-            });
-            if constexpr (Cl.nminus > 0) {
-                const T Km = ep - op;
-                const T mm = omg - gt;
-                sfor<0, Cl.nminus>([&](auto i) {
-                    constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
-                    S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), fma(mm, f[q], Km));
-                });
-            }
-        });
+        update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), cols[1],
+                                   A.d_flag);
     }
 
     // force table of the next step: on the extra blocks when there are any,
@@ -257,18 +153,294 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Row-marching form of the same step.  A wavefront owns a strip of 64 columns
+// and marches down a segment of rows [ya, yb).  Populations are loaded once per
+// row, aligned, and kept in a rolling window of registers:
+//   cur[q]  row y of every population,
+//   up[.]   row y-1 of the populations pulled from the row above (c_y > 0),
+//   dn[.]   row y+1 of the populations pulled from the row below (c_y < 0),
+//   pre[q]  the next row in flight (y+1, or y+2 for the c_y < 0 ones).
+// Horizontal neighbours come from the neighbouring lane (ds_bpermute); the edge
+// lane takes the strip's halo column, fetched for all populations of a row by
+// one gathered load (lane j holds the halo of the j-th population with
+// c_x != 0).  The per-site arithmetic is the same update_site as the tile form,
+// so both forms give bitwise identical results.
+// ---------------------------------------------------------------------------
+template <class St>
+struct MarchMap {
+    static constexpr int Q = St::Q;
+    static constexpr int cx(int q) { return St::dir[q].cx; }
+    static constexpr int cy(int q) { return St::dir[q].cy; }
+    static constexpr int count(int kind) {       // 0: c_y > 0, 1: c_y < 0
+        int n = 0;
+        for (int q = 0; q < Q; ++q) n += kind == 0 ? (cy(q) > 0) : (cy(q) < 0);
+        return n;
+    }
+    static constexpr int nU = count(0);
+    static constexpr int nD = count(1);
+    static constexpr int uidx(int q) {
+        int k = 0;
+        for (int p = 0; p < q; ++p) k += cy(p) > 0;
+        return k;
+    }
+    static constexpr int didx(int q) {
+        int k = 0;
+        for (int p = 0; p < q; ++p) k += cy(p) < 0;
+        return k;
+    }
+    // halo lanes: populations with c_x != 0, those with c_y >= 0 first
+    static constexpr int nHUZ() {
+        int k = 0;
+        for (int q = 0; q < Q; ++q) k += (cx(q) != 0 && cy(q) >= 0);
+        return k;
+    }
+    static constexpr int hidx(int q) {
+        int k = 0;
+        if (cy(q) >= 0) {
+            for (int p = 0; p < q; ++p) k += (cx(p) != 0 && cy(p) >= 0);
+            return k;
+        }
+        k = nHUZ();
+        for (int p = 0; p < q; ++p) k += (cx(p) != 0 && cy(p) < 0);
+        return k;
+    }
+    static constexpr int nH() {
+        int k = 0;
+        for (int q = 0; q < Q; ++q) k += cx(q) != 0;
+        return k;
+    }
+};
+
+template <class T>
+__device__ __forceinline__ T lane_from(T v, int addr_bytes) {
+    if constexpr (std::is_same<T, double>::value) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_ds_bpermute(addr_bytes, (int)(unsigned)(b & 0xffffffffu));
+        const int hi = __builtin_amdgcn_ds_bpermute(addr_bytes, (int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(addr_bytes, __float_as_int(v)));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T read_lane(T v, int lane) {
+    if constexpr (std::is_same<T, double>::value) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffu), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T write_lane(T old, T val, int lane) {
+    return (int)threadIdx.x == lane ? val : old;
+}
+
+template <class S, class St, bool UNIT, bool FORCED>
+__global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
+    using T = typename S::T;
+    using raw = typename S::raw;
+    using M = MarchMap<St>;
+    constexpr int Q = St::Q;
+    constexpr int NH = M::nH();
+    constexpr bool F64 = std::is_same<T, double>::value;
+
+    const int64_t step = *A.d_step + A.step_off;
+    const int par = (int)(step & 1);
+    const int lane = threadIdx.x;
+    const int wv = threadIdx.y;
+
+    // XCD-aware persistent schedule over groups of 4 consecutive strip
+    // segments (one per wavefront of the block)
+    const int G = A.tile_blocks;
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int nb = (G - xcd + 7) >> 3;
+    const int n_groups = (A.n_tiles + 3) >> 2;
+    const int chunk = (n_groups + 7) >> 3;
+    const int g_end = min(n_groups, (xcd + 1) * chunk);
+
+    for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
+        const int u = grp * 4 + wv;
+        if (u >= A.n_tiles) continue;
+        const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
+        const RealDesc& Dsc = A.desc[r];
+        const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
+        const int strips = uni(Dsc.tiles_x);
+        const int seglen = uni(Dsc.seglen);
+        const int local = u - uni(Dsc.tile_begin);
+        const int seg = local / strips;
+        const int strip = local - seg * strips;
+        const int ya = seg * seglen;
+        const int yb = min(ny, ya + seglen);
+        const int x0 = strip * kTileW;
+        const int R = min(kTileW - 1, nx - 1 - x0);      // last active lane
+        const int x = x0 + lane;
+        const bool active = lane <= R;
+        const long long plane_bytes = (long long)uni(Dsc.pitch) * (long long)sizeof(raw);
+        const long long rowq = plane_bytes * Q;
+        const char* src = (const char*)uni(Dsc.buf[par]);
+        char* dst = (char*)uni(Dsc.buf[par ^ 1]);
+        InterpW<T> W;
+        SiteCtx<T> sctx;
+        if constexpr (F64) {
+            W.set(uni(Dsc.a[0]), uni(Dsc.a[1]), uni(Dsc.a[2]));
+            sctx.ginv = uni(Dsc.inv_tau);
+            sctx.dt = uni(Dsc.dt);
+        } else {
+            W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
+            sctx.ginv = uni(Dsc.inv_tauf);
+            sctx.dt = uni(Dsc.dtf);
+        }
+        sctx.plane_bytes = plane_bytes;
+        sctx.K = -1;
+        sctx.gtab = nullptr;
+        T c1 = 0, s1 = 0;
+        if constexpr (FORCED) {
+            sctx.K = uni(Dsc.K);
+            sctx.gtab = uni((const T*)Dsc.g[par]);
+            if (sctx.K >= 0 && active) {
+                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
+                c1 = twx[2 * x];
+                s1 = twx[2 * x + 1];
+            }
+        }
+        const uint32_t colb = (uint32_t)(x * sizeof(raw));
+        auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
+        auto ld = [&](int q, int yy) -> T {
+            const char* rowp = src + (long long)wrap(yy) * rowq + (long long)q * plane_bytes;
+            return (T)S::ld((gp<const raw>)(rowp + colb));
+        };
+        // halo gather: lane j < NH holds the halo of the j-th population with c_x != 0,
+        // row yy (c_y >= 0 populations) or yy + 1 (c_y < 0 populations)
+        int my_q = 0, my_dy = 0;
+        bool my_left = true;
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            if constexpr (M::cx(q) != 0) {
+                if (lane == M::hidx(q)) {
+                    my_q = q;
+                    my_dy = M::cy(q) < 0 ? 1 : 0;
+                    my_left = M::cx(q) > 0;
+                }
+            }
+        });
+        const int hcol = my_left ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + R + 1 == nx ? 0 : x0 + R + 1);
+        auto gather = [&](int yy) -> T {
+            T h = 0;
+            if (lane < NH) {
+                const char* p = src + (long long)wrap(yy + my_dy) * rowq +
+                                (long long)my_q * plane_bytes + (long long)hcol * sizeof(raw);
+                h = (T)S::ld((gp<const raw>)p);
+            }
+            return h;
+        };
+
+        // prologue
+        T cur[Q], pre[Q], up[M::nU], dn[M::nD];
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            cur[q] = ld(q, ya);
+            if constexpr (M::cy(q) > 0) up[M::uidx(q)] = ld(q, ya - 1);
+            if constexpr (M::cy(q) < 0) dn[M::didx(q)] = ld(q, ya + 1);
+        });
+        T hp = gather(ya - 1);
+        T hc = gather(ya);
+        T hn = 0;
+
+        for (int y = ya; y < yb; ++y) {
+            if (y + 1 < yb) {                    // next row in flight
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    pre[q] = ld(q, M::cy(q) < 0 ? y + 2 : y + 1);
+                });
+                hn = gather(y + 1);
+            }
+            // (b) stream: pull by linear interpolation
+            T f[Q];
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                constexpr Dir d = St::dir[q];
+                constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+                const T own = cur[q];
+                T vert = own;
+                if constexpr (d.cy > 0) vert = up[M::uidx(q)];
+                if constexpr (d.cy < 0) vert = dn[M::didx(q)];
+                if constexpr (d.cx == 0 && d.cy == 0) {
+                    f[q] = own;
+                } else if constexpr (d.cx == 0) {
+                    if constexpr (UNIT && n == 1) f[q] = vert;
+                    else f[q] = lerp(own, vert, W.a[n - 1]);
+                } else {
+                    // x-neighbour upstream: lane - 1 for c_x > 0, lane + 1 for c_x < 0
+                    constexpr int H = M::hidx(q);
+                    const int addr = (lane - d.cx) * 4;
+                    const int fix = d.cx > 0 ? 0 : R;
+                    const T h_own = read_lane(d.cy < 0 ? hp : hc, H);   // halo, row y
+                    const T own_nb = write_lane(lane_from(own, addr), h_own, fix);
+                    if constexpr (d.cy == 0) {
+                        if constexpr (UNIT && n == 1) f[q] = own_nb;
+                        else f[q] = lerp(own, own_nb, W.a[n - 1]);
+                    } else {
+                        // halo of the upstream row: y-1 (in hp) or y+1 (in hc)
+                        const T h_vert = read_lane(d.cy > 0 ? hp : hc, H);
+                        const T vert_nb = write_lane(lane_from(vert, addr), h_vert, fix);
+                        f[q] = fma(W.w11[n - 1], vert_nb,
+                                   fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                    }
+                }
+            });
+            if (active)
+                update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + (long long)y * rowq),
+                                           colb, A.d_flag);
+            // roll the window
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                if constexpr (M::cy(q) > 0) {
+                    up[M::uidx(q)] = cur[q];
+                    cur[q] = pre[q];
+                } else if constexpr (M::cy(q) < 0) {
+                    cur[q] = dn[M::didx(q)];
+                    dn[M::didx(q)] = pre[q];
+                } else {
+                    cur[q] = pre[q];
+                }
+            });
+            hp = hc;
+            hc = hn;
+        }
+    }
+
+    if constexpr (FORCED) {
+        const int extra = (int)gridDim.x - G;
+        const int u0 = extra > 0 ? b - G : xcd + 8 * (b >> 3);
+        const int du = extra > 0 ? extra : 8 * nb;
+        for (int u = u0 >= 0 ? u0 : A.n_gitems; u < A.n_gitems; u += du) {
+            const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
+            const RealDesc& Dsc = A.desc[r];
+            force_item<T>(Dsc, u - uni(Dsc.gitem_begin), step + 1, kTileW * A.th);
+        }
+    }
+}
+
 template <class St, bool UNIT, bool FORCED>
-static const void* kernel_ptr() {
+static const void* kernel_ptr(int kind) {
+    if (kind == kKernelMarch) return (const void*)march_kernel<Store, St, UNIT, FORCED>;
     return (const void*)step_kernel<Store, St, UNIT, FORCED>;
 }
 
-static const void* select_kernel(int stencil, bool unit, bool forced) {
+static const void* select_kernel(int kind, int stencil, bool unit, bool forced) {
     if (stencil == RLBM_STENCIL_SPH26) {
-        if (unit) return forced ? kernel_ptr<Sph26, true, true>() : kernel_ptr<Sph26, true, false>();
-        return forced ? kernel_ptr<Sph26, false, true>() : kernel_ptr<Sph26, false, false>();
+        if (unit) return forced ? kernel_ptr<Sph26, true, true>(kind) : kernel_ptr<Sph26, true, false>(kind);
+        return forced ? kernel_ptr<Sph26, false, true>(kind) : kernel_ptr<Sph26, false, false>(kind);
     }
-    if (unit) return forced ? kernel_ptr<Circ8, true, true>() : kernel_ptr<Circ8, true, false>();
-    return forced ? kernel_ptr<Circ8, false, true>() : kernel_ptr<Circ8, false, false>();
+    if (unit) return forced ? kernel_ptr<Circ8, true, true>(kind) : kernel_ptr<Circ8, true, false>(kind);
+    return forced ? kernel_ptr<Circ8, false, true>(kind) : kernel_ptr<Circ8, false, false>(kind);
 }
 
 #if RLBM_STORAGE_ID == 0
@@ -286,7 +458,7 @@ static const void* select_kernel(int stencil, bool unit, bool forced) {
 #endif
 
 hipError_t RLBM_LAUNCH_NAME(const StepLaunch& L) {
-    const void* k = select_kernel(L.stencil, L.unit_cfl, L.forced);
+    const void* k = select_kernel(L.kind, L.stencil, L.unit_cfl, L.forced);
     StepArgs a = L.args;
     void* params[] = {&a};
     if (L.ev_start)
@@ -295,9 +467,9 @@ hipError_t RLBM_LAUNCH_NAME(const StepLaunch& L) {
     return hipLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, 0, L.stream);
 }
 
-int RLBM_OCC_NAME(int stencil, bool unit, bool forced, int th) {
+int RLBM_OCC_NAME(int kind, int stencil, bool unit, bool forced, int th) {
     int blocks = 0;
-    const void* k = select_kernel(stencil, unit, forced);
+    const void* k = select_kernel(kind, stencil, unit, forced);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kTileW * th, 0) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;

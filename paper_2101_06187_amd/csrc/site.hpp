@@ -279,6 +279,143 @@ __device__ __forceinline__ void eq_coeffs(double eps, double bx, double by, doub
     A0 = hp - eps * invD - C * b2 * invD;
 }
 
+
+// ---------------------------------------------------------------------------
+// The per-site part of the step after streaming (Sec. III C (c)-(e)): moments,
+// FP64 Landau frame, equilibrium coefficients, force field and projected force
+// term, Anderson-Witting collision, store of the new populations of this site
+// into the destination row drow at byte offset own.  f holds the streamed
+// populations (minus the storage shift); (c1, s1) = (cos, sin)(2 pi x / nx).
+// ---------------------------------------------------------------------------
+template <class T>
+struct SiteCtx {
+    T ginv, dt;
+    int K;                 // largest |kx| of the force table; -1 unforced
+    const T* gtab;         // force table of this step
+    long long plane_bytes;
+};
+
+template <class S, class St, bool FORCED, class T>
+__device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
+                                            T s1, int y, gp<char> drow, uint32_t own,
+                                            int* d_flag) {
+    using raw = typename S::raw;
+    constexpr int D = St::D;
+    const T ginv = ctx.ginv, dt = ctx.dt;
+    const int K = ctx.K;
+    const T* gtab = ctx.gtab;
+    const long long plane_bytes = ctx.plane_bytes;
+    // (c) moments, Landau frame in FP64
+    const Moments<T> m = moments<St, FORCED>(f);
+    const double E64 = (double)m.E + (double)S::shift;
+    const double dshift = (double)S::shift / D;     // sum_q w v_i v_i = 1/D per axis
+    double eps, bx64, by64;
+    const bool ok = landau64<D>(E64, (double)m.Jx, (double)m.Jy,
+                                (double)m.Pxx + dshift, (double)m.Pxy,
+                                (double)m.Pyy + dshift, eps, bx64, by64);
+    if (!ok) *d_flag = 1;
+
+    // (d) equilibrium F_eq - shift = A0' + B t + C t^2 (t = beta.v), and the
+    // Anderson-Witting rate omega = g (1 - t), g = gamma / tau.  For the +v
+    // and -v members of a class:
+    //   omega (F_eq - shift) = E(t) +- O(t),
+    //   E = g A0' + g (C - B) t^2,   O = g (B - A0') t - g C t^3.
+    double A0d, Bd, Cd, gam;
+    eq_coeffs<D>(eps, bx64, by64, A0d, Bd, Cd, gam);
+    const double A0s = A0d - (double)S::shift;
+    const double g64 = gam * (double)ginv;
+    const T g = (T)g64;
+    const T k0 = (T)(g64 * A0s), k1 = (T)(g64 * (Bd - A0s));
+    const T k2 = (T)(g64 * (Cd - Bd)), k3 = (T)(g64 * Cd);
+    const T omg = (T)(1.0 - g64);
+    const T bx = (T)bx64, by = (T)by64;
+
+    // force term: dF(v) = a + b.v + v.M.v (Sec. III C, App. B)
+    T fa = 0, fbx = 0, fby = 0, Mxx = 0, Mxy = 0, Myy = 0, Mzz = 0;
+    if constexpr (FORCED) {
+        // F_c(x, y) = sum_k cos(k a) P_c(k, y) - sin(k a) Q_c(k, y), a = 2 pi x / nx;
+        // cos/sin(k a) by the Chebyshev recurrence.
+        T Fx = 0, Fy = 0;
+        if (K >= 0) {                       // K < 0: this lattice is unforced
+            const gp<const T> grow = (gp<const T>)gtab + (size_t)y * (K + 1) * 4;
+            Fx = grow[0];
+            Fy = grow[2];
+            T cp = 1, sp = 0, ck = c1, sk = s1;
+            const T two_c1 = c1 + c1;
+            auto term = [&](T g0, T g1, T g2, T g3) {
+                Fx = fma(ck, g0, fma(-sk, g1, Fx));
+                Fy = fma(ck, g2, fma(-sk, g3, Fy));
+                const T cn = fma(two_c1, ck, -cp);
+                const T sn = fma(two_c1, sk, -sp);
+                cp = ck; sp = sk; ck = cn; sk = sn;
+            };
+            int k = 1;
+            for (; k + 3 <= K; k += 4) {      // four table rows per batch of loads
+                T gv[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) gv[i] = grow[4 * k + i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
+            }
+            for (; k <= K; ++k) term(grow[4 * k], grow[4 * k + 1], grow[4 * k + 2], grow[4 * k + 3]);
+        }
+        const T E = (T)E64;
+        fa = (T)(-0.5) * dt * (Fx * m.Jx + Fy * m.Jy);
+        fbx = dt * E * Fx;
+        fby = dt * E * Fy;
+        const T Sxx = Fx * m.Rxxx + Fy * m.Rxxy;
+        const T Sxy = Fx * m.Rxxy + Fy * m.Rxyy;
+        const T Syy = Fx * m.Rxyy + Fy * m.Ryyy;
+        const T k2f = (D == 3 ? (T)2.5 : (T)2.0) * dt;
+        Mxx = k2f * ((T)2 * Fx * m.Jx - Sxx);
+        Mxy = k2f * (Fx * m.Jy + Fy * m.Jx - Sxy);
+        Myy = k2f * ((T)2 * Fy * m.Jy - Syy);
+        if constexpr (D == 3) {
+            const T Rxzz = m.Jx - m.Rxxx - m.Rxyy;   // |v| = 1
+            const T Ryzz = m.Jy - m.Rxxy - m.Ryyy;
+            Mzz = -k2f * (Fx * Rxzz + Fy * Ryzz);
+        }
+    }
+
+    // (e) collide + force, store:  F' <- (1 - omega) F' + omega (F_eq - shift) + dF
+    sfor<0, St::NC>([&](auto ic) {
+        constexpr DirClass Cl = St::cls[ic];
+        constexpr double um = comp_mag(Cl.ncomp);
+        constexpr double ux = Cl.sx * um, uy = Cl.sy * um;
+        T t = 0;
+        if constexpr (ux != 0.0) t = (T)ux * bx;
+        if constexpr (uy != 0.0) t = fma((T)uy, by, t);
+        const T t2 = t * t;
+        const T Ev = fma(k2, t2, k0);
+        const T Ov = t * fma(-k3, t2, k1);
+        T dfe = fa, dfo = 0;
+        if constexpr (FORCED) {
+            if constexpr (ux != 0.0) dfe = fma((T)(ux * ux), Mxx, dfe);
+            if constexpr (ux != 0.0 && uy != 0.0) dfe = fma((T)(2.0 * ux * uy), Mxy, dfe);
+            if constexpr (uy != 0.0) dfe = fma((T)(uy * uy), Myy, dfe);
+            if constexpr (Cl.vz2 != 0.0) dfe = fma((T)Cl.vz2, Mzz, dfe);
+            if constexpr (ux != 0.0) dfo = (T)ux * fbx;
+            if constexpr (uy != 0.0) dfo = fma((T)uy, fby, dfo);
+        }
+        const T ep = Ev + dfe;
+        const T op = Ov + dfo;
+        const T gt = g * t;
+        const T Kp = ep + op;
+        const T mp = omg + gt;
+        sfor<0, Cl.nplus>([&](auto i) {
+            constexpr int q = Cl.first + decltype(i)::value;
+            S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), fma(mp, f[q], Kp));
+        });
+        if constexpr (Cl.nminus > 0) {
+            const T Km = ep - op;
+            const T mm = omg - gt;
+            sfor<0, Cl.nminus>([&](auto i) {
+                constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
+                S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), fma(mm, f[q], Km));
+            });
+        }
+    });
+}
 }  // namespace rlbm
 
 namespace rlbm {

@@ -180,23 +180,43 @@ def test_full_size_sampled_one_step(storage, n, shell, amp, tau):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("storage", ["F64", "F32"])
-def test_tile_shape_does_not_change_results(storage):
-    """Per-site arithmetic is independent of the launch shape: bitwise."""
-    n = 96
-    e, bx, by = workloads.noisy_rest(n + 8, n, 0.01, seed=4)
+@pytest.mark.parametrize("storage", ["F64", "F32", "F16S", "BF16S"])
+@pytest.mark.parametrize("shape", [(96, 104), (130, 37)])
+def test_kernel_form_and_shape_do_not_change_results(storage, shape):
+    """Per-site arithmetic is independent of the kernel form (tile / row
+    marching) and of the launch shape (tile height, segment length): bitwise,
+    also on a ragged lattice whose last strip is 2 columns wide."""
+    nx, ny = shape
+    e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=4)
     fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
     ref = None
-    for th in (1, 2, 4, 8):
-        lat = rl.Lattice(n, n + 8, 0.56, storage=storage, forcing=fr)
-        lat.set_tile(th)
+    for kind, param in [("tile", 1), ("tile", 2), ("tile", 4), ("tile", 8),
+                        ("march", 0), ("march", 1), ("march", 3), ("march", 16), ("march", 500)]:
+        lat = rl.Lattice(nx, ny, 0.56, storage=storage, forcing=fr)
+        lat.set_kernel(kind, param)
         lat.set_state(dev(e), dev(bx), dev(by))
         lat.step(5)
         F = host(lat.populations())
         if ref is None:
             ref = F
         else:
-            assert np.array_equal(F, ref), th
+            assert np.array_equal(F, ref), (kind, param)
+
+
+@pytest.mark.parametrize("kind", ["tile", "march"])
+def test_both_kernel_forms_match_oracle(kind):
+    """Random populations on a ragged lattice, forced, cfl < 1, both forms."""
+    nx, ny = 67, 13
+    F0 = workloads.random_populations(SPH.v, ny, nx, seed=77, spread=0.3)
+    force = dict(amplitude=3e-3, k_lo=1.0, k_hi=3.0, seed=8)
+    lat = rl.Lattice(nx, ny, 0.6, storage="F64", cfl=0.9,
+                     forcing=rl.Forcing(3e-3, 1.0, 3.0, 8))
+    lat.set_kernel(kind, 4 if kind == "march" else 2)
+    lat.set_populations(dev(oracle_to_lib(F0)))
+    lat.step(2)
+    F2 = lib_to_oracle(host(lat.populations()))
+    F2o = orlbm.run(F0, SPH, 0.6, 2, cfl=0.9, force=force)
+    assert rel(F2, F2o) < 1e-13
 
 
 def test_graph_replay_matches_direct_launches():
