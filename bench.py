@@ -66,10 +66,10 @@ def committed_traffic():
     return d.get("traffic_bytes_per_launch")
 
 
-def make_lattice(rl, wl, storage, torch):
+def make_lattice(rl, wl, storage, torch, stencil="SPH26"):
     import workloads
     A, klo, khi, fseed = wl.forcing
-    lat = rl.Lattice(wl.n, wl.n, wl.tau, storage=storage,
+    lat = rl.Lattice(wl.n, wl.n, wl.tau, stencil=stencil, storage=storage,
                      forcing=rl.Forcing(A, klo, khi, fseed))
     e, bx, by = workloads.initial_fields(wl)
     dev = lambda a: torch.from_numpy(a).to("cuda:0")  # noqa: E731
@@ -100,14 +100,15 @@ def field_error(a, b):
             "beta": float(max(np.abs(xa - xb).max(), np.abs(ya - yb).max()) / vmax)}
 
 
-def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n):
-    lat = make_lattice(rl, wl, storage, torch)
+def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH26"):
+    lat = make_lattice(rl, wl, storage, torch, stencil)
     ms = time_steps(lat, torch, steps, warmup, chunk)
     kms = lat.profile_step_kernel(prof_n)
     sites = wl.n * wl.n
-    algo = 2 * Q * BYTES[storage] * sites
+    algo = 2 * lat.Q * BYTES[storage] * sites
     out = {
         "storage": storage,
+        "stencil": stencil,
         "ms_per_step": ms,
         "mlups": sites / (ms * 1e-3) / 1e6,
         "kernel_ms": kms,
@@ -182,8 +183,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the HBM-resident 2048^2 / 8192^2 lines")
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--only", default=None, metavar="WORKLOAD:STORAGE",
-                    help="time one form only (e.g. forced2048:F32), for profiler runs")
+    ap.add_argument("--only", default=None, metavar="WORKLOAD:STORAGE[:STENCIL]",
+                    help="time one form only (e.g. forced2048:F32 or "
+                         "forced2048:F32:SPH26_ZFOLD), for profiler runs")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes 3 times "
                          "(counter calibration under rocprofv3 --pmc)")
@@ -211,9 +213,10 @@ def main():
         log(f"copy: 3 x {4 * n} bytes")
         del src, dst
     if a.only:
-        name, storage = a.only.split(":")
+        name, storage, *st = a.only.split(":")
         w = workloads.WORKLOADS[name]
-        lat, r = run_form(rl, torch, w, storage, a.steps, a.warmup, 50, min(a.steps, 200))
+        lat, r = run_form(rl, torch, w, storage, a.steps, a.warmup, 50, min(a.steps, 200),
+                          st[0] if st else "SPH26")
         r["unstable"] = lat.check() != rl.OK
         log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms'] * 1e3:.2f} us "
             f"= {r['kernel_gbs']:.0f} GB/s")
@@ -237,25 +240,42 @@ def main():
     for storage in ("F32", "F64", "F16S", "BF16S"):
         forms[storage]["unstable"] = lats[storage].check() != rl.OK
         lats[storage].close()
-    del lats, ref
+    del lats
+    torch.cuda.empty_cache()
+
+    # The z-folded stencil (17 stored populations, exact for the one-layer
+    # lattice): same workload, same step, fewer bytes per site.
+    for storage in ("F32", "F16S"):
+        key = storage + "_ZFOLD"
+        lat, r = run_form(rl, torch, wl, storage, a.steps, a.warmup, chunk, 500, "SPH26_ZFOLD")
+        r["field_error_vs_f64"] = field_error(lat.fields(), ref)
+        r["unstable"] = lat.check() != rl.OK
+        lat.close()
+        forms[key] = r
+        log(f"{key}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms'] * 1e3:.2f} us = "
+            f"{r['kernel_gbs']:.0f} GB/s, field error vs F64 {r['field_error_vs_f64']}")
+    del ref
     torch.cuda.empty_cache()
 
     extra = {}
     if not a.no_extra:
-        for name, storages, steps in (("forced2048", ("F32", "F16S", "BF16S"), 300),
-                                      ("forced8192", ("F32", "F16S"), 60)):
+        for name, storages, steps in (
+                ("forced2048", ("F32", "F16S", "BF16S", "F32_ZFOLD", "F16S_ZFOLD"), 300),
+                ("forced8192", ("F32", "F16S", "F32_ZFOLD", "F16S_ZFOLD"), 60)):
             w = workloads.WORKLOADS[name]
             extra[name] = {}
-            for storage in storages:
-                lat, r = run_form(rl, torch, w, storage, steps, 20, 20, 20)
+            for key in storages:
+                storage, _, fold = key.partition("_")
+                lat, r = run_form(rl, torch, w, storage, steps, 20, 20, 20,
+                                  "SPH26_ZFOLD" if fold else "SPH26")
                 r["unstable"] = lat.check() != rl.OK
                 lat.close()
                 del lat
                 torch.cuda.empty_cache()
-                extra[name][storage] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms",
-                                                          "kernel_gbs", "kernel_frac_hbm_peak",
-                                                          "unstable", "kernel_form")}
-                log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
+                extra[name][key] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms",
+                                                      "kernel_gbs", "kernel_frac_hbm_peak",
+                                                      "unstable", "kernel_form")}
+                log(f"{name} {key}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
                     f"({100 * r['kernel_frac_hbm_peak']:.1f}% of HBM peak)")
 
     if not a.no_extra:

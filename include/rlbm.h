@@ -61,13 +61,18 @@ extern "C" {
  *   zero momentum has weight 0 (a massless particle cannot be at rest) and is
  *   not stored.  P = eps/3.
  * CIRC8: 2+1-dimensional analogue, 8 in-plane directions at 2 pi q/8, weights
- *   1/8, P = eps/2 (the 2D massless ideal gas).  Not the paper's stencil.    */
-enum { RLBM_STENCIL_SPH26 = 0, RLBM_STENCIL_CIRC8 = 1 };
+ *   1/8, P = eps/2 (the 2D massless ideal gas).  Not the paper's stencil.
+ * SPH26_ZFOLD: SPH26 with each z-mirror pair (a, b, +c) / (a, b, -c) stored
+ *   once at the summed weight (17 populations).  Every state of the one-layer
+ *   lattice of Sec. V is mirror symmetric, so the dynamics are those of SPH26
+ *   exactly; bytes per site drop from 26 to 17 populations.               */
+enum { RLBM_STENCIL_SPH26 = 0, RLBM_STENCIL_CIRC8 = 1, RLBM_STENCIL_SPH26_ZFOLD = 2 };
 
 /* Population storage in HBM.  Arithmetic: FP64 for RLBM_F64, FP32 otherwise;
- * the Landau-frame solve is FP64 in every form.  F16S/BF16S store F_q - 1
- * (the rest equilibrium at eps = 1 is F_q = 1 for every q), rounded to nearest
- * even.                                                                     */
+ * the Landau-frame solve is FP64 in every form.  F32, F16S and BF16S store the
+ * deviation F_q - 1 from the rest equilibrium at eps = 1 (F_q = 1 for every q),
+ * rounded to nearest even; F64 stores F_q.  rlbm_get/set_populations convert,
+ * so callers always see F_q.                                                */
 enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_F16S = 2, RLBM_BF16S = 3 };
 
 /* ---- parameter blocks ----------------------------------------------------- */
@@ -98,7 +103,7 @@ const char* rlbm_status_string(int status);
 const char* rlbm_last_error(void);
 
 /* Direction table of a stencil in the library's storage order.
- * *h_q receives Q (26 or 8); h_v (3*Q doubles, may be NULL) the unit vectors
+ * *h_q receives Q (26, 8 or 17); h_v (3*Q doubles, may be NULL) the unit vectors
  * (vx, vy, vz) per direction; h_w (Q doubles, may be NULL) the weights.
  * Pure host function.                                                      */
 int rlbm_stencil_info(int stencil, int32_t* h_q, double* h_v, double* h_w);

@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
-STENCILS = {"SPH26": 0, "CIRC8": 1}
+STENCILS = {"SPH26": 0, "CIRC8": 1, "SPH26_ZFOLD": 2}
 STORAGES = {"F64": 0, "F32": 1, "F16S": 2, "BF16S": 3}
 KERNELS = {"tile": 0, "march": 1}
 
@@ -187,7 +187,7 @@ class Lattice:
         self.nx, self.ny, self.tau = int(nx), int(ny), float(tau)
         self.stencil, self.storage, self.cfl, self.forcing = stencil, storage, float(cfl), forcing
         self.device = torch.device(device)
-        self.Q = 26 if stencil == "SPH26" else 8
+        self.Q = len(stencil_info(stencil)[1])
         nbytes = workspace_bytes(nx, ny, stencil, storage, forcing, cfl)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -313,7 +313,7 @@ class Ensemble:
         self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
         self.n = len(self.sizes)
         self.device = torch.device(device)
-        self.Q = 26 if stencil == "SPH26" else 8
+        self.Q = len(stencil_info(stencil)[1])
         lats = (_Lattice * self.n)(*[_lattice(nx, ny, cfl) for nx, ny in self.sizes])
         t = (ctypes.c_double * self.n)(*[float(x) for x in taus])
         fr = None

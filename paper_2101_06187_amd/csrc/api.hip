@@ -37,8 +37,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int storage_bytes(int storage) {
     return storage == RLBM_F64 ? 8 : (storage == RLBM_F32 ? 4 : 2);
 }
-int stencil_q(int stencil) { return stencil == RLBM_STENCIL_SPH26 ? 26 : 8; }
-int stencil_d(int stencil) { return stencil == RLBM_STENCIL_SPH26 ? 3 : 2; }
+int stencil_q(int stencil) {
+    return stencil == RLBM_STENCIL_SPH26 ? 26 : (stencil == RLBM_STENCIL_SPH26_ZFOLD ? 17 : 8);
+}
 
 struct ModeTable {
     std::vector<int4> modes;    // grouped by |kx|: (kx, ky, m, 0)
@@ -394,7 +395,8 @@ int engine_bytes(int n_real, const rlbm_lattice* lats, int stencil, int storage,
                  const rlbm_forcing* forcings, size_t* out) {
     if (!lats || !out) return fail(RLBM_EINVAL, "NULL argument");
     if (n_real < 1 || n_real > 65535) return fail(RLBM_EINVAL, "n_real must be in [1, 65535]");
-    if (stencil != RLBM_STENCIL_SPH26 && stencil != RLBM_STENCIL_CIRC8)
+    if (stencil != RLBM_STENCIL_SPH26 && stencil != RLBM_STENCIL_CIRC8 &&
+        stencil != RLBM_STENCIL_SPH26_ZFOLD)
         return fail(RLBM_EINVAL, "unknown stencil");
     if (storage < RLBM_F64 || storage > RLBM_BF16S) return fail(RLBM_EINVAL, "unknown storage");
     std::vector<ModeTable> mts(n_real);
@@ -607,6 +609,7 @@ int rlbm_stencil_info(int stencil, int32_t* h_q, double* h_v, double* h_w) {
     };
     if (stencil == RLBM_STENCIL_SPH26) fill(Sph26{});
     else if (stencil == RLBM_STENCIL_CIRC8) fill(Circ8{});
+    else if (stencil == RLBM_STENCIL_SPH26_ZFOLD) fill(Sph17{});
     else return fail(RLBM_EINVAL, "unknown stencil");
     return RLBM_OK;
 }
@@ -693,7 +696,7 @@ int rlbm_get_populations(rlbm_ctx* ctx, double* d_out) {
     if (int rc = check_ctx(ctx)) return rc;
     if (!d_out) return fail(RLBM_EINVAL, "NULL output");
     Engine& E = ctx->e;
-    HIPCHK(launch_get_populations(E.d_desc, 0, E.storage, E.Q, E.lats[0].nx, E.lats[0].ny, d_out,
+    HIPCHK(launch_get_populations(E.d_desc, 0, E.storage, E.stencil, E.lats[0].nx, E.lats[0].ny, d_out,
                                   E.parity(), E.stream));
     return RLBM_OK;
 }
@@ -704,7 +707,7 @@ int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in) {
     Engine& E = ctx->e;
     HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
     E.step = 0;
-    HIPCHK(launch_set_populations(E.d_desc, 0, E.storage, E.Q, E.lats[0].nx, E.lats[0].ny, d_in,
+    HIPCHK(launch_set_populations(E.d_desc, 0, E.storage, E.stencil, E.lats[0].nx, E.lats[0].ny, d_in,
                                   E.parity(), E.stream));
     return E.prime_force_table();
 }
@@ -994,7 +997,7 @@ int rlbm_batch_get_populations(rlbm_batch* b, int32_t r, double* d_out) {
     if (int rc = check_ctx(b)) return rc;
     if (r < 0 || r >= b->e.n_real || !d_out) return fail(RLBM_EINVAL, "bad arguments");
     Engine& E = b->e;
-    HIPCHK(launch_get_populations(E.d_desc, r, E.storage, E.Q, E.lats[r].nx, E.lats[r].ny, d_out,
+    HIPCHK(launch_get_populations(E.d_desc, r, E.storage, E.stencil, E.lats[r].nx, E.lats[r].ny, d_out,
                                   E.parity(), E.stream));
     return RLBM_OK;
 }

@@ -93,10 +93,10 @@ hipError_t launch_reset(int64_t* d_step, int64_t value, int* d_flag, hipStream_t
 hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int stencil,
                             int nx, int ny, const double* e, const double* ux,
                             const double* uy, int parity, hipStream_t s);
-hipError_t launch_set_populations(const RealDesc* d_desc, int r, int storage, int Q,
+hipError_t launch_set_populations(const RealDesc* d_desc, int r, int storage, int stencil,
                                   int nx, int ny, const double* in, int parity,
                                   hipStream_t s);
-hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, int Q,
+hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, int stencil,
                                   int nx, int ny, double* out, int parity,
                                   hipStream_t s);
 hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil,

@@ -350,6 +350,7 @@ static hipError_t dispatch(int storage, int stencil, Args&&... args) {
     auto go = [&](auto s_tag) -> hipError_t {
         using S = decltype(s_tag);
         if (stencil == RLBM_STENCIL_SPH26) return Fn<S, Sph26>::run(args...);
+        if (stencil == RLBM_STENCIL_SPH26_ZFOLD) return Fn<S, Sph17>::run(args...);
         return Fn<S, Circ8>::run(args...);
     };
     switch (storage) {
@@ -419,16 +420,13 @@ hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int sten
                             int parity, hipStream_t s) {
     return dispatch<SetStateFn>(storage, stencil, d_desc, r, nx, ny, e, ux, uy, parity, s);
 }
-hipError_t launch_set_populations(const RealDesc* d_desc, int r, int storage, int Q, int nx,
-                                  int ny, const double* in, int parity, hipStream_t s) {
-    (void)Q;
-    return dispatch<SetPopFn>(storage, Q == 26 ? RLBM_STENCIL_SPH26 : RLBM_STENCIL_CIRC8, d_desc,
-                              r, nx, ny, in, parity, s);
+hipError_t launch_set_populations(const RealDesc* d_desc, int r, int storage, int stencil,
+                                  int nx, int ny, const double* in, int parity, hipStream_t s) {
+    return dispatch<SetPopFn>(storage, stencil, d_desc, r, nx, ny, in, parity, s);
 }
-hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, int Q, int nx,
-                                  int ny, double* out, int parity, hipStream_t s) {
-    return dispatch<GetPopFn>(storage, Q == 26 ? RLBM_STENCIL_SPH26 : RLBM_STENCIL_CIRC8, d_desc,
-                              r, nx, ny, out, parity, s);
+hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, int stencil,
+                                  int nx, int ny, double* out, int parity, hipStream_t s) {
+    return dispatch<GetPopFn>(storage, stencil, d_desc, r, nx, ny, out, parity, s);
 }
 hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil, bool unit_cfl,
                          int nx, int ny, int parity, double* e, double* ux, double* uy,

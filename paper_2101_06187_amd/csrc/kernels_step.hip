@@ -439,6 +439,10 @@ static const void* select_kernel(int kind, int stencil, bool unit, bool forced) 
         if (unit) return forced ? kernel_ptr<Sph26, true, true>(kind) : kernel_ptr<Sph26, true, false>(kind);
         return forced ? kernel_ptr<Sph26, false, true>(kind) : kernel_ptr<Sph26, false, false>(kind);
     }
+    if (stencil == RLBM_STENCIL_SPH26_ZFOLD) {
+        if (unit) return forced ? kernel_ptr<Sph17, true, true>(kind) : kernel_ptr<Sph17, true, false>(kind);
+        return forced ? kernel_ptr<Sph17, false, true>(kind) : kernel_ptr<Sph17, false, false>(kind);
+    }
     if (unit) return forced ? kernel_ptr<Circ8, true, true>(kind) : kernel_ptr<Circ8, true, false>(kind);
     return forced ? kernel_ptr<Circ8, false, true>(kind) : kernel_ptr<Circ8, false, false>(kind);
 }

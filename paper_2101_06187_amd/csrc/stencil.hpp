@@ -69,6 +69,38 @@ struct Sph26 {
     };
 };
 
+// z-mirror fold of Sph26.  Every state of the one-layer (N x N x 1) model is
+// symmetric under v_z -> -v_z, so the two members of each mirror pair carry the
+// same population; they are stored once, at the summed weight.  The members
+// with v_z != 0 are represented by v_z > 0 (only |v_z| enters the step).
+struct Sph17 {
+    static constexpr int Q = 17;
+    static constexpr int NC = 9;
+    static constexpr int D = 3;        // angular dimension: P = eps / 3
+    static constexpr Dir dir[Q] = {
+        {1, 0, 0},  {-1, 0, 0},                                     // class 0: x faces
+        {0, 1, 0},  {0, -1, 0},                                     // class 1: y faces
+        {0, 0, 1},                                                  // class 2: z faces (pair)
+        {1, 1, 0},  {-1, -1, 0},                                    // class 3
+        {1, -1, 0}, {-1, 1, 0},                                     // class 4
+        {1, 0, 1},  {-1, 0, 1},                                     // class 5: xz edges (pairs)
+        {0, 1, 1},  {0, -1, 1},                                     // class 6: yz edges (pairs)
+        {1, 1, 1},  {-1, -1, 1},                                    // class 7: corners (pairs)
+        {1, -1, 1}, {-1, 1, 1},                                     // class 8: corners (pairs)
+    };
+    static constexpr DirClass cls[NC] = {
+        {0, 1, 1, 1, 1, 0, 0.0, 1.0 / 21.0},
+        {2, 1, 1, 1, 0, 1, 0.0, 1.0 / 21.0},
+        {4, 1, 0, 1, 0, 0, 1.0, 2.0 / 21.0},
+        {5, 1, 1, 2, 1, 1, 0.0, 4.0 / 105.0},
+        {7, 1, 1, 2, 1, -1, 0.0, 4.0 / 105.0},
+        {9, 1, 1, 2, 1, 0, 0.5, 8.0 / 105.0},
+        {11, 1, 1, 2, 0, 1, 0.5, 8.0 / 105.0},
+        {13, 1, 1, 3, 1, 1, 1.0 / 3.0, 9.0 / 140.0},
+        {15, 1, 1, 3, 1, -1, 1.0 / 3.0, 9.0 / 140.0},
+    };
+};
+
 struct Circ8 {
     static constexpr int Q = 8;
     static constexpr int NC = 4;

@@ -119,3 +119,31 @@ def oracle_step_at(patches, st, tau, cfl, force=None, step_index=0, sites=None, 
             Fn = Fn + orlbm.force_source(T, R, fx, fy, cfl, st)
         out[:, s] = Fn[:, 1, 1]
     return out
+
+
+def fold_maps():
+    """For each direction of the library's z-folded SPH26 table: the oracle
+    (SPH26) index of the same direction and of its z mirror."""
+    v, _ = rl.stencil_info("SPH26_ZFOLD")
+    st = ostencil.sph26()
+    up = np.array([int(np.argmin(np.abs(st.v - v[q]).max(axis=1))) for q in range(len(v))])
+    mv = v * np.array([1.0, 1.0, -1.0])
+    dn = np.array([int(np.argmin(np.abs(st.v - mv[q]).max(axis=1))) for q in range(len(v))])
+    assert sorted(set(up) | set(dn)) == list(range(26))
+    return up, dn
+
+
+def fold(F_or):
+    """Oracle SPH26 populations (z-mirror symmetric) -> folded library order."""
+    up, dn = fold_maps()
+    assert np.array_equal(F_or[up], F_or[dn])
+    return np.ascontiguousarray(F_or[up])
+
+
+def unfold(F_lib):
+    """Folded library populations -> oracle SPH26 order (mirror pairs equal)."""
+    up, dn = fold_maps()
+    out = np.empty((26,) + F_lib.shape[1:], dtype=F_lib.dtype)
+    out[up] = F_lib
+    out[dn] = F_lib
+    return out

@@ -63,6 +63,34 @@ def test_stencil_classes_are_antipodal():
     assert q == 26
 
 
+def test_zfold_table_is_the_mirror_sum_of_sph26():
+    """The folded table: one representative (v_z >= 0) per z-mirror pair of
+    the oracle's SPH26 set, at the pair's summed weight; angular averages of
+    every mirror-even monomial up to degree 7 agree with the full set."""
+    v, w = rl.stencil_info("SPH26_ZFOLD")
+    st = ostencil.sph26()
+    assert v.shape == (17, 3) and np.all(v[:, 2] >= 0)
+    covered = []
+    for q in range(17):
+        for sz in (1.0, -1.0):
+            d = np.abs(st.v - v[q] * np.array([1.0, 1.0, sz])).max(axis=1)
+            assert d.min() < 1e-15
+            covered.append(int(np.argmin(d)))
+    mirror_pairs = {covered[2 * q]: covered[2 * q + 1] for q in range(17)}
+    assert set(covered) == set(range(26))
+    for q in range(17):
+        j, k = covered[2 * q], covered[2 * q + 1]
+        want = st.w[j] if j == k else st.w[j] + st.w[k]
+        assert abs(w[q] - want) < 1e-17
+    assert len(mirror_pairs) == 17
+    for a in range(8):
+        for b in range(8 - a):
+            for c in range(0, 8 - a - b, 2):
+                full = np.sum(st.w * st.v[:, 0] ** a * st.v[:, 1] ** b * st.v[:, 2] ** c)
+                fold = np.sum(w * v[:, 0] ** a * v[:, 1] ** b * v[:, 2] ** c)
+                assert abs(full - fold) < 1e-15, (a, b, c)
+
+
 @pytest.mark.parametrize("n,shell", [(512, (4, 6)), (2048, (8, 12)), (64, (2, 4)),
                                      (8192, (32, 40)), (48, (3.0, 7.5)), (100, (1, 1.5))])
 def test_forcing_modes_match_oracle(n, shell):
@@ -82,6 +110,13 @@ def test_forcing_modes_nyquist_rejected():
 def test_workspace_bytes(storage, s):
     b = rl.workspace_bytes(512, 512, "SPH26", storage, rl.Forcing(1e-5, 4, 6, 2))
     assert 2 * 26 * 512 * 512 * s <= b <= 2 * 26 * 512 * 512 * s + (1 << 20)
+
+
+def test_zfold_workspace_is_17_of_26():
+    a = rl.workspace_bytes(512, 512, "SPH26", "F32")
+    b = rl.workspace_bytes(512, 512, "SPH26_ZFOLD", "F32")
+    assert 2 * 17 * 512 * 512 * 4 <= b < a
+    assert b - 2 * 17 * 512 * 512 * 4 == a - 2 * 26 * 512 * 512 * 4
 
 
 def _init(**kw):
