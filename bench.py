@@ -12,10 +12,13 @@ HBM before timing starts.
 
 The headline value is the FP32-population step in MLUPS.  The same line
 carries the FP64, F16S and BF16S forms of the step (MLUPS, kernel GB/s and
-their field error against the FP64 path after the same steps), the same
-kernel on HBM-resident lattices (2048^2 and 8192^2), the roofline of the
-FP32 step kernel (per-launch duration from HIP events around every launch)
-and the FP64 NumPy oracle timed on the host cores for a bounded sample.
+their field error against the FP64 path after the same steps), the z-folded
+stencil (17 stored populations, exact for the one-layer lattice) in F32 and
+F16S, the same kernels on HBM-resident lattices (2048^2 and 8192^2) and on
+the 256-lattice ensemble, the roofline of the FP32 step kernel (per-launch
+duration from HIP events around every launch; HBM traffic from the committed
+rocprofv3 counter summary when it matches the kernel sources) and the FP64
+NumPy oracle timed on the host cores for a bounded sample.
 Everything except the JSON line goes to stderr.
 """
 import argparse
@@ -50,20 +53,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """HBM bytes per launch of the FP32 step kernel on this workload from the
-    committed rocprofv3 counter summary, if it was taken on the current
-    kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
+def committed_traffic(tag="forced512_F32"):
+    """HBM bytes per launch of the step kernel on a workload, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on
+    the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.md")
     if not os.path.exists(path):
         return None
-    try:
-        d = json.load(open(path))
-    except ValueError:
+    sha, val = None, None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 2 and f[0] == "kernel_src_sha":
+            sha = f[1]
+        elif len(f) == 3 and f[0] == tag and f[1] == "traffic_bytes_per_launch":
+            val = int(f[2])
+    if sha != kernel_source_hash():
         return None
-    if d.get("kernel_src_sha") != kernel_source_hash():
-        return None
-    return d.get("traffic_bytes_per_launch")
+    return val
 
 
 def make_lattice(rl, wl, storage, torch, stencil="SPH26"):
@@ -275,6 +281,8 @@ def main():
                 extra[name][key] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms",
                                                       "kernel_gbs", "kernel_frac_hbm_peak",
                                                       "unstable", "kernel_form")}
+                extra[name][key]["traffic_bytes_per_launch"] = committed_traffic(
+                    f"{name}_{storage}" + ("_SPH26_ZFOLD" if fold else ""))
                 log(f"{name} {key}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
                     f"({100 * r['kernel_frac_hbm_peak']:.1f}% of HBM peak)")
 
