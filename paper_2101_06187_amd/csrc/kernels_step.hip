@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
     const int64_t step = *A.d_step + A.step_off;
     const int par = (int)(step & 1);
     const int lane = threadIdx.x;
-    const int wv = threadIdx.y;
+    const int wv = uni((int)threadIdx.y);   // one wavefront per row of the block
 
     // XCD-aware persistent schedule over groups of 4 consecutive strip
     // segments (one per wavefront of the block)
