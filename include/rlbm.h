@@ -133,6 +133,20 @@ int rlbm_init(rlbm_ctx** out, const rlbm_lattice* lat, double tau, int stencil,
               const rlbm_forcing* forcing, int storage,
               void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* Relaxation time of the Anderson-Witting term (Sec. III A: tau_R =
+ * 5 (eta/s) / T).
+ *   RLBM_TAU_CONSTANT (default) -- tau_R / dt = tau at every site.
+ *   RLBM_TAU_ETA_S              -- eta/s constant instead: the temperature of
+ *     the massless gas is T = T0 (eps / eps_ref)^(1/4) with T0 = eps_ref = 1,
+ *     so the local relaxation time is tau(eps) = tau * eps^(-1/4), tau being
+ *     its value at eps = 1, i.e. tau = 5 (eta/s) / (T0 dt) (the paper's runs,
+ *     eta/s = 0.01 and dt = 0.05 time units, give tau = 1).  The scheme needs
+ *     tau(eps) > 1/2, i.e. eps < (2 tau)^4, everywhere.
+ * Takes effect from the next step; recorded in checkpoints.  EINVAL for an
+ * unknown mode.  Synchronises.                                             */
+enum { RLBM_TAU_CONSTANT = 0, RLBM_TAU_ETA_S = 1 };
+int rlbm_set_relaxation(rlbm_ctx* ctx, int32_t mode);
+
 /* Step (a) of Sec. III C: F_q := F_eq,q(eps, beta) at every site (the
  * truncated Juettner equilibrium of Sec. III B), step counter := 0, stability
  * flag cleared.  d_e, d_ux, d_uy: FP64 [ny][nx] device arrays of the Landau
@@ -182,7 +196,7 @@ int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
                   double* h_Ek, int32_t nbins, double* h_enstrophy);
 
 /* Checkpoint: a self-describing host blob (header: lattice, stencil,
- * storage, tau, forcing, step counter; then the populations in the storage
+ * storage, tau and relaxation mode, forcing, step counter; then the populations in the storage
  * type).  A run resumed from it continues bit for bit, because the forcing
  * is counter-based.  rlbm_load rejects a blob of another configuration
  * (EINVAL).  Both synchronise.                                             */
@@ -243,6 +257,8 @@ int rlbm_batch_fields(rlbm_batch* b, int32_t r, double* d_e, double* d_ux,
                       double* d_uy, double* d_T);
 int rlbm_batch_get_populations(rlbm_batch* b, int32_t r, double* d_out);
 int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk);
+/* rlbm_set_relaxation for every lattice of the ensemble.                   */
+int rlbm_batch_set_relaxation(rlbm_batch* b, int32_t mode);
 void rlbm_batch_destroy(rlbm_batch* b);
 
 #ifdef __cplusplus

@@ -155,6 +155,22 @@ def collide(Fs, Feq, beta, tau, st):
     return Fs - omega * (Fs - Feq)
 
 
+def relaxation_time(eps, tau, eta_s=False):
+    """Relaxation time of each site, in time steps.
+
+    Sec. III A: the viscosity is eta = tau_R (eps + P)/5 with
+    tau_R = 5 (eta/s) / T.  With ``eta_s`` False, tau_R / dt = tau everywhere
+    (constant relaxation time).  With ``eta_s`` True, eta/s is held constant
+    instead, so tau_R scales as 1/T; for massless particles the energy density
+    goes as T^4, and with the lattice normalisation T0 = 1 at eps = 1 the
+    local temperature is T = eps^(1/4), giving tau(eps) = tau * eps^(-1/4)
+    (``tau`` is the relaxation time at eps = 1, i.e. 5 (eta/s) / dt).
+    """
+    if not eta_s:
+        return tau
+    return tau * eps ** -0.25
+
+
 def force_source(T, R, fx, fy, dt, st, T0=1.0):
     """Population increment of the projected stirring-force term.
 
@@ -237,12 +253,13 @@ def check_physical(eps, beta):
         raise FloatingPointError("unphysical state (eps <= 0, |beta| >= 1 or non-finite)")
 
 
-def step(F, st, tau, cfl=1.0, force=None, step_index=0, realization=0):
+def step(F, st, tau, cfl=1.0, force=None, step_index=0, realization=0, eta_s=False):
     """One RLBM time step, in the order of Sec. III C: (b) stream, (c) moments
     and Landau frame, (d) equilibrium, (e) collide and add the force term.
 
     ``force`` is None (unforced) or a dict with keys amplitude, k_lo, k_hi,
     seed; the force of this step is drawn with ``step_index`` (Philox counter).
+    ``eta_s`` selects the constant-eta/s relaxation time (``relaxation_time``).
     """
     Fs = stream(F, st, cfl)
     T, R = moments(Fs, st)
@@ -250,7 +267,7 @@ def step(F, st, tau, cfl=1.0, force=None, step_index=0, realization=0):
     beta = u[1:] / u[0]
     check_physical(eps, beta)
     Feq = equilibrium(eps, beta, st)
-    Fn = collide(Fs, Feq, beta, tau, st)
+    Fn = collide(Fs, Feq, beta, relaxation_time(eps, tau, eta_s), st)
     if force is not None and force.get("amplitude", 0.0) != 0.0:
         ny, nx = F.shape[1:]
         fx, fy = _forcing.force_field(nx, ny, force["amplitude"], force["k_lo"],
@@ -260,7 +277,7 @@ def step(F, st, tau, cfl=1.0, force=None, step_index=0, realization=0):
     return Fn
 
 
-def run(F, st, tau, n, cfl=1.0, force=None, first_step=0, realization=0):
+def run(F, st, tau, n, cfl=1.0, force=None, first_step=0, realization=0, eta_s=False):
     for s in range(n):
-        F = step(F, st, tau, cfl, force, first_step + s, realization)
+        F = step(F, st, tau, cfl, force, first_step + s, realization, eta_s)
     return F

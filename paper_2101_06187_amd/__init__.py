@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "librlbm.so")
 STENCILS = {"SPH26": 0, "CIRC8": 1, "SPH26_ZFOLD": 2}
 STORAGES = {"F64": 0, "F32": 1, "F16S": 2, "BF16S": 3}
 KERNELS = {"tile": 0, "march": 1}
+RELAXATION = {"constant": 0, "eta_s": 1}
 
 OK, EINVAL, ENOSPACE, EHIP, EUNSTABLE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 
@@ -88,6 +89,7 @@ SIGNATURES = [
     ("rlbm_set_tile", _I, [_P, _I32]),
     ("rlbm_autotune", _I, [_P, _I32, _P]),
     ("rlbm_set_graph_chunk", _I, [_P, _I32]),
+    ("rlbm_set_relaxation", _I, [_P, _I32]),
     ("rlbm_profile_step_kernel", _I, [_P, _I64, _P]),
     ("rlbm_destroy", None, [_P]),
     ("rlbm_batch_workspace_bytes", _I, [_I32, _P, _I, _I, _P, _P]),
@@ -98,6 +100,7 @@ SIGNATURES = [
     ("rlbm_batch_fields", _I, [_P, _I32, _P, _P, _P, _P]),
     ("rlbm_batch_get_populations", _I, [_P, _I32, _P]),
     ("rlbm_batch_set_graph_chunk", _I, [_P, _I32]),
+    ("rlbm_batch_set_relaxation", _I, [_P, _I32]),
     ("rlbm_batch_destroy", None, [_P]),
 ]
 
@@ -285,6 +288,10 @@ class Lattice:
     def set_graph_chunk(self, chunk):
         _check(lib().rlbm_set_graph_chunk(self._ctx, int(chunk)))
 
+    def set_relaxation(self, mode):
+        """mode "constant" (tau everywhere) or "eta_s" (tau(eps) = tau eps^-1/4)."""
+        _check(lib().rlbm_set_relaxation(self._ctx, RELAXATION[mode]))
+
     def profile_step_kernel(self, n):
         """Advance n steps; mean duration (ms) of the fused step kernel, from
         HIP events recorded around each launch on the library's stream."""
@@ -357,6 +364,9 @@ class Ensemble:
 
     def set_graph_chunk(self, chunk):
         _check(lib().rlbm_batch_set_graph_chunk(self._b, int(chunk)))
+
+    def set_relaxation(self, mode):
+        _check(lib().rlbm_batch_set_relaxation(self._b, RELAXATION[mode]))
 
     def close(self):
         if self._b:

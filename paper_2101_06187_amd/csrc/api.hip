@@ -535,6 +535,16 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
 
 int check_ctx(const void* p) { return p ? RLBM_OK : fail(RLBM_EINVAL, "context is NULL"); }
 
+int engine_set_relaxation(Engine& E, int mode) {
+    if (mode != RLBM_TAU_CONSTANT && mode != RLBM_TAU_ETA_S)
+        return fail(RLBM_EINVAL, "unknown relaxation mode");
+    for (RealDesc& d : E.hdesc) d.tau_mode = mode;
+    HIPCHK(hipMemcpyAsync(E.d_desc, E.hdesc.data(), sizeof(RealDesc) * E.n_real,
+                          hipMemcpyHostToDevice, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    return RLBM_OK;
+}
+
 int engine_set_state(Engine& E, int r, const double* d_e, const double* d_ux,
                      const double* d_uy, bool reset_step) {
     if (!d_e || !d_ux || !d_uy) return fail(RLBM_EINVAL, "NULL field pointer");
@@ -564,7 +574,7 @@ int engine_check(Engine& E) {
 // checkpoint header
 struct SaveHeader {
     char magic[8];
-    int32_t version, stencil, storage, nx, ny, Q;
+    int32_t version, stencil, storage, nx, ny, Q, tau_mode, reserved;
     int64_t step;
     double tau, cfl, amplitude, k_lo, k_hi;
     uint64_t seed;
@@ -803,7 +813,8 @@ int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes) {
     SaveHeader h;
     std::memset(&h, 0, sizeof(h));
     std::memcpy(h.magic, "RLBMSAV1", 8);
-    h.version = 1;
+    h.version = 2;
+    h.tau_mode = E.hdesc[0].tau_mode;
     h.stencil = E.stencil;
     h.storage = E.storage;
     h.nx = E.lats[0].nx;
@@ -836,12 +847,13 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
     Engine& E = ctx->e;
     SaveHeader h;
     std::memcpy(&h, h_buf, sizeof(h));
-    if (std::memcmp(h.magic, "RLBMSAV1", 8) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, "RLBMSAV1", 8) != 0 || h.version != 2)
         return fail(RLBM_EINVAL, "not a checkpoint of this library");
     if (h.stencil != E.stencil || h.storage != E.storage || h.nx != E.lats[0].nx ||
         h.ny != E.lats[0].ny || h.Q != E.Q || h.tau != E.taus[0] || h.cfl != E.lats[0].cfl ||
         h.amplitude != E.frc[0].amplitude || h.k_lo != E.frc[0].k_lo ||
-        h.k_hi != E.frc[0].k_hi || h.seed != E.frc[0].seed || h.step < 0)
+        h.k_hi != E.frc[0].k_hi || h.seed != E.frc[0].seed ||
+        h.tau_mode != E.hdesc[0].tau_mode || h.step < 0)
         return fail(RLBM_EINVAL, "checkpoint of another configuration");
     E.step = h.step;
     HIPCHK(launch_reset(E.d_step, h.step, E.d_flag, E.stream));
@@ -940,6 +952,11 @@ int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk) {
     return RLBM_OK;
 }
 
+int rlbm_set_relaxation(rlbm_ctx* ctx, int32_t mode) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return engine_set_relaxation(ctx->e, mode);
+}
+
 int rlbm_profile_step_kernel(rlbm_ctx* ctx, int64_t n, double* h_ms) {
     if (int rc = check_ctx(ctx)) return rc;
     if (!h_ms) return fail(RLBM_EINVAL, "NULL output");
@@ -1007,6 +1024,11 @@ int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk) {
     if (chunk < 0 || chunk > 4096) return fail(RLBM_EINVAL, "chunk must be in [0, 4096]");
     b->e.graph_chunk = chunk;
     return RLBM_OK;
+}
+
+int rlbm_batch_set_relaxation(rlbm_batch* b, int32_t mode) {
+    if (int rc = check_ctx(b)) return rc;
+    return engine_set_relaxation(b->e, mode);
 }
 
 void rlbm_batch_destroy(rlbm_batch* b) { delete b; }

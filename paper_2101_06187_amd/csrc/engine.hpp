@@ -33,6 +33,7 @@ struct RealDesc {
     int K;                        // largest |kx| of the driven modes; -1 unforced
     int n_modes;
     int realization;              // Philox counter word 2
+    int tau_mode;                 // RLBM_TAU_CONSTANT or RLBM_TAU_ETA_S
     int gitem_begin;              // first force-table work item of this lattice
     uint64_t seed;
     double amplitude;

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     char* dst = nullptr;
     InterpW<T> W;
     T ginv = 0, dt = 0;
+    int eta_s = 0;
     const T* twp = nullptr;
     const T* gtab = nullptr;
     int txi = 0, tyi = 0, t_prev = -1;
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
                 ginv = uni(Dsc.inv_tauf);
                 dt = uni(Dsc.dtf);
             }
+            eta_s = uni(Dsc.tau_mode);
             if constexpr (FORCED) {
                 K = uni(Dsc.K);
                 twp = uni((const T*)Dsc.twx);
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
         T f[St::Q];
         stream_pull<S, St, UNIT>(rows, plane_bytes, cols, W, f);
 
-        const SiteCtx<T> sctx{ginv, dt, K, gtab, plane_bytes};
+        const SiteCtx<T> sctx{ginv, dt, K, gtab, plane_bytes, eta_s};
         T c1 = 0, s1 = 0;
         if constexpr (FORCED) {
             if (K >= 0) {
@@ -299,6 +301,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
         }
         sctx.plane_bytes = plane_bytes;
         sctx.K = -1;
+        sctx.eta_s = uni(Dsc.tau_mode);
         sctx.gtab = nullptr;
         T c1 = 0, s1 = 0;
         if constexpr (FORCED) {

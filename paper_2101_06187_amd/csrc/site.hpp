@@ -293,6 +293,7 @@ struct SiteCtx {
     int K;                 // largest |kx| of the force table; -1 unforced
     const T* gtab;         // force table of this step
     long long plane_bytes;
+    int eta_s;             // 1: relaxation time tau(eps) = tau eps^(-1/4) (constant eta/s)
 };
 
 template <class S, class St, bool FORCED, class T>
@@ -323,7 +324,10 @@ __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T
     double A0d, Bd, Cd, gam;
     eq_coeffs<D>(eps, bx64, by64, A0d, Bd, Cd, gam);
     const double A0s = A0d - (double)S::shift;
-    const double g64 = gam * (double)ginv;
+    double g64 = gam * (double)ginv;
+    // constant eta/s (Sec. III A): tau_R = 5 (eta/s) / T with T = eps^(1/4)
+    // for massless particles at T0 = 1, so 1/tau scales as eps^(1/4)
+    if (ctx.eta_s) g64 *= sqrt(sqrt(eps));
     const T g = (T)g64;
     const T k0 = (T)(g64 * A0s), k1 = (T)(g64 * (Bd - A0s));
     const T k2 = (T)(g64 * (Cd - Bd)), k3 = (T)(g64 * Cd);

@@ -145,5 +145,7 @@ def test_null_context_calls_fail_cleanly():
     L = rl.lib()
     assert L.rlbm_step(None, 1) == rl.EINVAL
     assert L.rlbm_fields(None, None, None, None, None) == rl.EINVAL
+    assert L.rlbm_set_relaxation(None, 1) == rl.EINVAL
+    assert L.rlbm_batch_set_relaxation(None, 1) == rl.EINVAL
     L.rlbm_destroy(None)
     L.rlbm_batch_destroy(None)
