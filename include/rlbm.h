@@ -195,6 +195,22 @@ int rlbm_spectrum_scratch_bytes(const rlbm_ctx* ctx, size_t* h_bytes);
 int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
                   double* h_Ek, int32_t nbins, double* h_enstrophy);
 
+/* Velocity with the driven band removed (Sec. V: the recorded velocities are
+ * filtered in Fourier space so that the driven wave numbers do not
+ * contribute).  beta of the current fields (as rlbm_fields) is transformed,
+ * every mode with k_lo^2 <= kx^2 + ky^2 <= k_hi^2 (integer k in
+ * [-n/2, n/2)^2, the shell test of the forcing modes) is set to zero, and the
+ * field is transformed back.  d_ux, d_uy: [ny][nx] FP64 device outputs, either
+ * may be NULL.  h_mean_speed, if not NULL, receives the lattice average of
+ * |beta_filtered| (the filtered average fluid velocity by which the paper
+ * tunes the forcing amplitude) and the call synchronises.  k_hi may be
+ * +infinity (remove everything from k_lo up, the paper's k_f <= k < k_max).
+ * Same scratch and power-of-two requirement as rlbm_spectrum.  EINVAL unless
+ * 0 <= k_lo <= k_hi.                                                       */
+int rlbm_filtered_velocity(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
+                           double k_lo, double k_hi, double* d_ux, double* d_uy,
+                           double* h_mean_speed);
+
 /* Checkpoint: a self-describing host blob (header: lattice, stencil,
  * storage, tau and relaxation mode, forcing, step counter; then the populations in the storage
  * type).  A run resumed from it continues bit for bit, because the forcing

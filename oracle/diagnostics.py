@@ -16,6 +16,9 @@ spectrum    -- Sec. IV: E(k) is the kinetic energy per wave-number magnitude.
                Enstrophy (Sec. IV, vorticity w = curl v):
                    Z = 1/2 sum_k |w_hat(k)|^2,
                    w_hat = i (2 pi kx / nx) beta_hat_y - i (2 pi ky / ny) beta_hat_x.
+filtered_velocity -- Sec. V: the recorded velocities have the driven band
+               removed in Fourier space; their lattice average speed is the
+               quantity the forcing amplitude is tuned by.
 """
 import numpy as np
 
@@ -56,3 +59,22 @@ def spectrum(beta_x, beta_y, nbins):
     w = 1j * (2 * np.pi * KX / nx) * by - 1j * (2 * np.pi * KY / ny) * bx
     Z = 0.5 * (np.abs(w) ** 2).sum()
     return Ek, Z
+
+
+def filtered_velocity(beta_x, beta_y, k_lo, k_hi):
+    """Velocity with the driven band removed, and its average speed.
+
+    Sec. V: every Fourier mode of beta with k_lo <= |k| <= k_hi (integer k in
+    [-n/2, n/2)^2, the same shell test as the forcing modes) is set to zero and
+    the field transformed back; the average fluid velocity is the lattice
+    mean of |beta_filtered|.
+    """
+    ny, nx = beta_x.shape
+    kx = np.fft.fftfreq(nx, 1.0 / nx)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    KY, KX = np.meshgrid(ky, kx, indexing="ij")
+    k2 = KX ** 2 + KY ** 2
+    keep = ~((k2 >= k_lo * k_lo) & (k2 <= k_hi * k_hi))
+    fx = np.fft.ifft2(np.fft.fft2(beta_x) * keep).real
+    fy = np.fft.ifft2(np.fft.fft2(beta_y) * keep).real
+    return fx, fy, float(np.mean(np.sqrt(fx ** 2 + fy ** 2)))

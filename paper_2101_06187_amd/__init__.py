@@ -81,6 +81,7 @@ SIGNATURES = [
     ("rlbm_set_populations", _I, [_P, _P]),
     ("rlbm_spectrum_scratch_bytes", _I, [_P, _P]),
     ("rlbm_spectrum", _I, [_P, _P, _SZ, _P, _I32, _P]),
+    ("rlbm_filtered_velocity", _I, [_P, _P, _SZ, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     ("rlbm_state_bytes", _I, [_P, _P]),
     ("rlbm_save", _I, [_P, _P, _SZ]),
     ("rlbm_load", _I, [_P, _P, _SZ]),
@@ -254,6 +255,20 @@ class Lattice:
         _check(lib().rlbm_spectrum(self._ctx, ctypes.c_void_p(p), n.value, Ek.ctypes.data_as(_P),
                                    nbins, ctypes.byref(Z)))
         return Ek, Z.value
+
+    def filtered_velocity(self, k_lo, k_hi):
+        """beta with the Fourier band k_lo <= |k| <= k_hi removed: (ux, uy, mean speed)."""
+        import torch
+        n = ctypes.c_size_t()
+        _check(lib().rlbm_spectrum_scratch_bytes(self._ctx, ctypes.byref(n)))
+        scratch = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        p = (scratch.data_ptr() + 255) // 256 * 256
+        ux = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        uy = torch.empty_like(ux)
+        speed = ctypes.c_double()
+        _check(lib().rlbm_filtered_velocity(self._ctx, ctypes.c_void_p(p), n.value, float(k_lo),
+                                            float(k_hi), _ptr(ux), _ptr(uy), ctypes.byref(speed)))
+        return ux, uy, speed.value
 
     # -- checkpoints and launch shape ---------------------------------------------
     def save(self):

@@ -724,6 +724,25 @@ int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in) {
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Forward 2-D DFT by radix-2 Stockham passes, ping-ponging between a and b
+// (rows with the x twiddles at sc + otx, then columns with sc + oty); returns
+// the buffer holding the result, or NULL if a launch failed.
+static double2* fft2_forward(Engine& E, char* sc, double2* a, double2* b, size_t otx,
+                             size_t oty) {
+    const int nx = E.lats[0].nx, ny = E.lats[0].ny;
+    for (int ns = 1; ns < nx; ns *= 2) {   // rows (x)
+        if (launch_fft_pass(a, b, (const double2*)(sc + otx), nx, ns, 1, nx, ny, E.stream) != hipSuccess)
+            return nullptr;
+        std::swap(a, b);
+    }
+    for (int ns = 1; ns < ny; ns *= 2) {   // columns (y)
+        if (launch_fft_pass(a, b, (const double2*)(sc + oty), ny, ns, nx, 1, nx, E.stream) != hipSuccess)
+            return nullptr;
+        std::swap(a, b);
+    }
+    return a;
+}
+
 static size_t spectrum_layout(int nx, int ny, size_t* o_z2, size_t* o_twx, size_t* o_twy,
                               size_t* o_bins, size_t* o_part, size_t* o_out, int* max_bins) {
     const size_t n = (size_t)nx * ny;
@@ -747,22 +766,19 @@ int rlbm_spectrum_scratch_bytes(const rlbm_ctx* ctx, size_t* h_bytes) {
     return RLBM_OK;
 }
 
-int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double* h_Ek,
-                  int32_t nbins, double* h_enstrophy) {
-    if (int rc = check_ctx(ctx)) return rc;
-    Engine& E = ctx->e;
+// Forward 2-D DFT of beta_x + i beta_y of the current fields into the
+// spectrum scratch; *out points at the transform (one of the two halves).
+static int spectrum_transform(Engine& E, void* d_scratch, size_t scratch_bytes, double2** out,
+                              int* max_bins) {
     const int nx = E.lats[0].nx, ny = E.lats[0].ny;
     if (!is_pow2(nx) || !is_pow2(ny))
         return fail(RLBM_EUNSUPPORTED, "the spectrum needs power-of-two lattice sides");
-    if (!d_scratch || !h_Ek || nbins < 1) return fail(RLBM_EINVAL, "bad spectrum arguments");
+    if (!d_scratch) return fail(RLBM_EINVAL, "NULL scratch");
     size_t oz2, otx, oty, obins, opart, oout;
-    int max_bins;
-    const size_t need = spectrum_layout(nx, ny, &oz2, &otx, &oty, &obins, &opart, &oout, &max_bins);
+    const size_t need = spectrum_layout(nx, ny, &oz2, &otx, &oty, &obins, &opart, &oout, max_bins);
     if (scratch_bytes < need) return fail(RLBM_ENOSPACE, "spectrum scratch too small");
     if ((uintptr_t)d_scratch % kAlign) return fail(RLBM_EINVAL, "scratch must be 256-byte aligned");
     char* sc = (char*)d_scratch;
-    double2* z = (double2*)sc;
-    double2* z2 = (double2*)(sc + oz2);
     std::vector<double2> twx(nx / 2 + 1), twy(ny / 2 + 1);
     for (int m = 0; m < nx / 2; ++m)
         twx[m] = make_double2(std::cos(2.0 * M_PI * m / nx), -std::sin(2.0 * M_PI * m / nx));
@@ -772,17 +788,25 @@ int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double* 
                           hipMemcpyHostToDevice, E.stream));
     HIPCHK(hipMemcpyAsync(sc + oty, twy.data(), sizeof(double2) * twy.size(),
                           hipMemcpyHostToDevice, E.stream));
+    double2* z = (double2*)sc;
     if (int rc = engine_fields(E, 0, nullptr, nullptr, nullptr, nullptr, z)) return rc;
-    double2* a = z;
-    double2* b = z2;
-    for (int ns = 1; ns < nx; ns *= 2) {   // rows (x)
-        HIPCHK(launch_fft_pass(a, b, (const double2*)(sc + otx), nx, ns, 1, nx, ny, E.stream));
-        std::swap(a, b);
-    }
-    for (int ns = 1; ns < ny; ns *= 2) {   // columns (y)
-        HIPCHK(launch_fft_pass(a, b, (const double2*)(sc + oty), ny, ns, nx, 1, nx, E.stream));
-        std::swap(a, b);
-    }
+    *out = fft2_forward(E, sc, z, (double2*)(sc + oz2), otx, oty);
+    if (!*out) return fail(RLBM_EHIP, "FFT pass launch failed");
+    return RLBM_OK;
+}
+
+int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double* h_Ek,
+                  int32_t nbins, double* h_enstrophy) {
+    if (int rc = check_ctx(ctx)) return rc;
+    Engine& E = ctx->e;
+    if (!h_Ek || nbins < 1) return fail(RLBM_EINVAL, "bad spectrum arguments");
+    const int nx = E.lats[0].nx, ny = E.lats[0].ny;
+    double2* a = nullptr;
+    int max_bins = 0;
+    if (int rc = spectrum_transform(E, d_scratch, scratch_bytes, &a, &max_bins)) return rc;
+    size_t oz2, otx, oty, obins, opart, oout;
+    spectrum_layout(nx, ny, &oz2, &otx, &oty, &obins, &opart, &oout, &max_bins);
+    char* sc = (char*)d_scratch;
     const int nb = std::min(nbins, max_bins);
     HIPCHK(launch_spectrum_bins(a, nx, ny, nb, (double*)(sc + obins), (double*)(sc + opart),
                                 spectrum_partials(nx, ny), (double*)(sc + oout), E.stream));
@@ -792,6 +816,34 @@ int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double* 
     HIPCHK(hipMemcpyAsync(&zz, sc + oout, sizeof(double), hipMemcpyDeviceToHost, E.stream));
     HIPCHK(hipStreamSynchronize(E.stream));
     if (h_enstrophy) *h_enstrophy = 0.5 * zz;
+    return RLBM_OK;
+}
+
+int rlbm_filtered_velocity(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double k_lo,
+                           double k_hi, double* d_ux, double* d_uy, double* h_mean_speed) {
+    if (int rc = check_ctx(ctx)) return rc;
+    Engine& E = ctx->e;
+    if (!(k_lo >= 0.0) || !(k_hi >= k_lo)) return fail(RLBM_EINVAL, "band must satisfy 0 <= k_lo <= k_hi");
+    const int nx = E.lats[0].nx, ny = E.lats[0].ny;
+    double2* a = nullptr;
+    int max_bins = 0;
+    if (int rc = spectrum_transform(E, d_scratch, scratch_bytes, &a, &max_bins)) return rc;
+    size_t oz2, otx, oty, obins, opart, oout;
+    spectrum_layout(nx, ny, &oz2, &otx, &oty, &obins, &opart, &oout, &max_bins);
+    char* sc = (char*)d_scratch;
+    const double hi2 = std::isfinite(k_hi) ? k_hi * k_hi : HUGE_VAL;
+    HIPCHK(launch_band_conj(a, nx, ny, k_lo * k_lo, hi2, E.stream));
+    double2* other = a == (double2*)sc ? (double2*)(sc + oz2) : (double2*)sc;
+    double2* w = fft2_forward(E, sc, a, other, otx, oty);
+    if (!w) return fail(RLBM_EHIP, "FFT pass launch failed");
+    HIPCHK(launch_unpack_speed(w, nx, ny, d_ux, d_uy, (double*)(sc + opart),
+                               spectrum_partials(nx, ny), (double*)(sc + oout), E.stream));
+    if (h_mean_speed) {
+        double s = 0;
+        HIPCHK(hipMemcpyAsync(&s, sc + oout, sizeof(double), hipMemcpyDeviceToHost, E.stream));
+        HIPCHK(hipStreamSynchronize(E.stream));
+        *h_mean_speed = s / ((double)nx * (double)ny);
+    }
     return RLBM_OK;
 }
 

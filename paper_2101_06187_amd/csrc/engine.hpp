@@ -115,5 +115,8 @@ hipError_t launch_spectrum_bins(const double2* Z, int nx, int ny, int nbins,
                                 double* out_bins, double* partials, int n_partials,
                                 double* out_z, hipStream_t s);
 int spectrum_partials(int nx, int ny);
+hipError_t launch_band_conj(double2* Z, int nx, int ny, double lo2, double hi2, hipStream_t s);
+hipError_t launch_unpack_speed(const double2* W, int nx, int ny, double* ux, double* uy,
+                               double* partials, int n_partials, double* out, hipStream_t s);
 
 }  // namespace rlbm

@@ -1,6 +1,8 @@
 // Auxiliary kernels: stirring-force table, step counter, initial state,
 // population import/export, macroscopic fields, conserved sums, FFT passes
 // and the shell-binned energy spectrum.
+#include <algorithm>
+
 #include "site.hpp"
 
 namespace rlbm {
@@ -240,6 +242,59 @@ hipError_t launch_fft_pass(const double2* in, double2* out, const double2* tw, i
     const long long work = (long long)(n / 2) * batch;
     hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
                        in, out, tw, n, ns, es, bs, batch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// driven-band filter (Sec. V).  Z = DFT(beta_x + i beta_y); a mode and its
+// mirror -k have the same |k|, so zeroing Z(k) on the band removes the band
+// from both components.  The inverse transform is done as a forward one of
+// the conjugate: band_conj zeroes the band and conjugates the rest, the
+// forward passes follow, unpack conjugates back, scales by 1/(nx ny), writes
+// the two components and sums |beta| per block (fixed order).
+// ---------------------------------------------------------------------------
+__global__ void band_conj_kernel(double2* Z, int nx, int ny, double lo2, double hi2) {
+    const long long n = (long long)nx * ny;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int iy = (int)(i / nx), ix = (int)(i - (long long)iy * nx);
+        const long long kx = ix < nx / 2 ? ix : ix - nx;
+        const long long ky = iy < ny / 2 ? iy : iy - ny;
+        const double k2 = (double)(kx * kx + ky * ky);
+        const double2 v = Z[i];
+        Z[i] = (k2 >= lo2 && k2 <= hi2) ? make_double2(0.0, 0.0) : make_double2(v.x, -v.y);
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+unpack_speed_kernel(const double2* W, int nx, int ny, double* ux, double* uy, double* partials) {
+    const long long n = (long long)nx * ny;
+    const double inv = 1.0 / ((double)nx * (double)ny);
+    double acc[1] = {0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const double2 v = W[i];
+        const double bx = v.x * inv, by = -v.y * inv;
+        if (ux) ux[i] = bx;
+        if (uy) uy[i] = by;
+        acc[0] += sqrt(bx * bx + by * by);
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
+hipError_t launch_band_conj(double2* Z, int nx, int ny, double lo2, double hi2, hipStream_t s) {
+    const long long n = (long long)nx * ny;
+    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(band_conj_kernel, dim3(blocks), dim3(256), 0, s, Z, nx, ny, lo2, hi2);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_speed(const double2* W, int nx, int ny, double* ux, double* uy,
+                               double* partials, int n_partials, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(unpack_speed_kernel, dim3(n_partials), dim3(kRedThreads), 0, s, W, nx, ny,
+                       ux, uy, partials);
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, n_partials,
+                       1, out);
     return hipGetLastError();
 }
 

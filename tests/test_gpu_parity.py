@@ -286,10 +286,32 @@ def test_spectrum_matches_oracle(n):
     assert abs(Z - Zo) < 1e-12 * Zo
 
 
+@pytest.mark.parametrize("n,band", [(64, (3.5, 6.5)), (256, (6.0, float("inf"))),
+                                    (128, (0.0, 0.5)), (64, (100.0, 200.0))])
+def test_filtered_velocity_matches_oracle(n, band):
+    """Driven-band filter (Sec. V): the GPU fields with the band removed and
+    their mean speed against the oracle's filter of the same fields."""
+    e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=7)
+    lat = rl.Lattice(n, n, 0.6, storage="F64", forcing=rl.Forcing(1e-4, 4, 6, 3))
+    lat.set_state(dev(e), dev(bx), dev(by))
+    lat.step(2)
+    _, gx, gy, _ = gpu_fields(lat)
+    fx, fy, speed = lat.filtered_velocity(*band)
+    ox, oy, ospeed = odiag.filtered_velocity(gx, gy, *band)
+    scale = max(np.abs(gx).max(), np.abs(gy).max())
+    say("filter", n, band, np.abs(host(fx) - ox).max() / scale, abs(speed - ospeed) / ospeed)
+    assert np.abs(host(fx) - ox).max() < 1e-12 * scale
+    assert np.abs(host(fy) - oy).max() < 1e-12 * scale
+    assert abs(speed - ospeed) < 1e-12 * ospeed
+
+
 def test_spectrum_rejects_non_power_of_two():
     lat = rl.Lattice(48, 48, 0.6)
     with pytest.raises(rl.RlbmError) as ex:
         lat.spectrum(10)
+    assert ex.value.code == rl.EUNSUPPORTED
+    with pytest.raises(rl.RlbmError) as ex:
+        lat.filtered_velocity(2.0, 4.0)
     assert ex.value.code == rl.EUNSUPPORTED
 
 

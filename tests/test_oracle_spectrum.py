@@ -1,5 +1,6 @@
 """Pins of the oracle's energy spectrum and enstrophy (Sec. IV) by Parseval's
-identity and single-mode closed forms."""
+identity and single-mode closed forms, and of the driven-band velocity filter
+(Sec. V) by plane-wave closed forms and consistency with the spectrum."""
 import numpy as np
 
 from oracle import diagnostics
@@ -32,3 +33,32 @@ def test_enstrophy_equals_mean_square_vorticity():
     w = np.fft.ifft2(1j * 2 * np.pi / n * (KX * np.fft.fft2(by) - KY * np.fft.fft2(bx)))
     _, Z = diagnostics.spectrum(bx, by, nbins=4)
     assert abs(Z - 0.5 * (np.abs(w) ** 2).mean()) < 1e-15
+
+
+def test_band_filter_removes_exactly_the_driven_modes():
+    """A field of three plane waves, one inside the band [5.5, 8.5]: the filter
+    returns the other two exactly (closed form), and the mean speed is that of
+    the remaining field."""
+    n = 32
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep_x = 0.01 * np.sin(2 * np.pi * 2 * y / n)              # |k| = 2
+    keep_y = 0.02 * np.cos(2 * np.pi * (3 * x + 1 * y) / n)    # |k| = sqrt(10)
+    band = 0.03 * np.cos(2 * np.pi * (5 * x + 4 * y) / n + 0.3)   # |k| = sqrt(41) = 6.4
+    fx, fy, speed = diagnostics.filtered_velocity(keep_x + band, keep_y - 2 * band, 5.5, 8.5)
+    assert np.abs(fx - keep_x).max() < 1e-15
+    assert np.abs(fy - keep_y).max() < 1e-15
+    assert abs(speed - np.mean(np.hypot(keep_x, keep_y))) < 1e-15
+
+
+def test_band_filter_beyond_the_lattice_is_identity_and_consistent_with_spectrum():
+    g = np.random.Generator(np.random.Philox(5))
+    bx, by = 0.01 * g.standard_normal((2, 16, 16))
+    fx, fy, _ = diagnostics.filtered_velocity(bx, by, 100.0, 200.0)
+    assert np.abs(fx - bx).max() < 1e-16 and np.abs(fy - by).max() < 1e-16
+    # removing the shells |k| in [2.5, 4.5] removes spectrum bins 3 and 4 only
+    fx, fy, _ = diagnostics.filtered_velocity(bx, by, 2.5, 4.5)
+    E0, _ = diagnostics.spectrum(bx, by, 12)
+    E1, _ = diagnostics.spectrum(fx, fy, 12)
+    want = E0.copy()
+    want[3:5] = 0.0
+    assert np.abs(E1 - want).max() < 1e-18
