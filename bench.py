@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the HBM-resident 2048^2 / 8192^2 lines")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--only", default=None, metavar="WORKLOAD:STORAGE[:STENCIL]",
                     help="time one form only (e.g. forced2048:F32 or "
                          "forced2048:F32:SPH26_ZFOLD), for profiler runs")

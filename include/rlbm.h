@@ -211,6 +211,18 @@ int rlbm_filtered_velocity(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
                            double k_lo, double k_hi, double* d_ux, double* d_uy,
                            double* h_mean_speed);
 
+/* Time-averaged spectrum and its error estimate (the paper's appendix on the
+ * minimum simulation time): from M spectra sampled every N steps, N being a
+ * decorrelation interval,
+ *   <E(k)> = (1/M) sum_i E_i(k),
+ *   err(k) = (1/M) sum_i sqrt(| <E(k)>^2 - E_i(k)^2 |)
+ * (reading: the printed expression under the root can be negative, so its
+ * magnitude is taken).  h_samples: M x nbins, row-major (sample i at
+ * h_samples + i * nbins); h_mean, h_err: nbins doubles (h_err may be NULL).
+ * Pure host function.  EINVAL for M < 1, nbins < 1 or NULL pointers.       */
+int rlbm_spectrum_average(const double* h_samples, int32_t n_samples, int32_t nbins,
+                          double* h_mean, double* h_err);
+
 /* Checkpoint: a self-describing host blob (header: lattice, stencil,
  * storage, tau and relaxation mode, forcing, step counter; then the populations in the storage
  * type).  A run resumed from it continues bit for bit, because the forcing

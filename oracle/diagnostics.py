@@ -19,6 +19,8 @@ spectrum    -- Sec. IV: E(k) is the kinetic energy per wave-number magnitude.
 filtered_velocity -- Sec. V: the recorded velocities have the driven band
                removed in Fourier space; their lattice average speed is the
                quantity the forcing amplitude is tuned by.
+spectrum_average -- appendix on the minimum simulation time: time average of
+               sampled spectra and the paper's error estimate.
 """
 import numpy as np
 
@@ -78,3 +80,14 @@ def filtered_velocity(beta_x, beta_y, k_lo, k_hi):
     fx = np.fft.ifft2(np.fft.fft2(beta_x) * keep).real
     fy = np.fft.ifft2(np.fft.fft2(beta_y) * keep).real
     return fx, fy, float(np.mean(np.sqrt(fx ** 2 + fy ** 2)))
+
+
+def spectrum_average(samples):
+    """Mean spectrum and error estimate of M spectra sampled a decorrelation
+    interval apart (appendix on the minimum simulation time): the error of
+    bin k is the sample average of sqrt(<E(k)>^2 - E_i(k)^2), read with the
+    magnitude of the difference under the root (it can be negative)."""
+    samples = np.asarray(samples, dtype=np.float64)
+    mean = samples.mean(axis=0)
+    err = np.sqrt(np.abs(mean[None, :] ** 2 - samples ** 2)).mean(axis=0)
+    return mean, err

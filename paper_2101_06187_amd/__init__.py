@@ -82,6 +82,7 @@ SIGNATURES = [
     ("rlbm_spectrum_scratch_bytes", _I, [_P, _P]),
     ("rlbm_spectrum", _I, [_P, _P, _SZ, _P, _I32, _P]),
     ("rlbm_filtered_velocity", _I, [_P, _P, _SZ, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    ("rlbm_spectrum_average", _I, [_P, _I32, _I32, _P, _P]),
     ("rlbm_state_bytes", _I, [_P, _P]),
     ("rlbm_save", _I, [_P, _P, _SZ]),
     ("rlbm_load", _I, [_P, _P, _SZ]),
@@ -180,6 +181,16 @@ def _f64(t, shape):
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
         raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
     return t
+
+
+def spectrum_average(samples):
+    """Time average and error estimate of sampled spectra (M x nbins array)."""
+    a = np.ascontiguousarray(samples, dtype=np.float64)
+    m, nb = a.shape
+    mean, err = np.zeros(nb), np.zeros(nb)
+    _check(lib().rlbm_spectrum_average(a.ctypes.data_as(_P), m, nb, mean.ctypes.data_as(_P),
+                                       err.ctypes.data_as(_P)))
+    return mean, err
 
 
 class Lattice:

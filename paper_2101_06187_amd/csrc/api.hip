@@ -643,6 +643,28 @@ int rlbm_forcing_modes(const rlbm_lattice* lat, const rlbm_forcing* forcing, int
     return RLBM_OK;
 }
 
+int rlbm_spectrum_average(const double* h_samples, int32_t n_samples, int32_t nbins,
+                          double* h_mean, double* h_err) {
+    if (!h_samples || n_samples < 1 || nbins < 1 || !h_mean)
+        return fail(RLBM_EINVAL, "bad spectrum-average arguments");
+    const double inv = 1.0 / n_samples;
+    for (int b = 0; b < nbins; ++b) {
+        double s = 0;
+        for (int i = 0; i < n_samples; ++i) s += h_samples[(size_t)i * nbins + b];
+        const double m = s * inv;
+        h_mean[b] = m;
+        if (h_err) {
+            double e = 0;
+            for (int i = 0; i < n_samples; ++i) {
+                const double v = h_samples[(size_t)i * nbins + b];
+                e += std::sqrt(std::fabs(m * m - v * v));
+            }
+            h_err[b] = e * inv;
+        }
+    }
+    return RLBM_OK;
+}
+
 int rlbm_workspace_bytes(const rlbm_lattice* lat, int stencil, int storage,
                          const rlbm_forcing* forcing, size_t* h_bytes) {
     return engine_bytes(1, lat, stencil, storage, forcing, h_bytes);

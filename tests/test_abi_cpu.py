@@ -149,3 +149,15 @@ def test_null_context_calls_fail_cleanly():
     assert L.rlbm_batch_set_relaxation(None, 1) == rl.EINVAL
     L.rlbm_destroy(None)
     L.rlbm_batch_destroy(None)
+
+
+def test_spectrum_average_matches_oracle():
+    from oracle import diagnostics
+    g = np.random.Generator(np.random.Philox(9))
+    S = g.random((11, 17)) * np.geomspace(1.0, 1e-6, 17)
+    mean, err = rl.spectrum_average(S)
+    om, oe = diagnostics.spectrum_average(S)
+    assert np.abs(mean - om).max() <= 1e-15 * np.abs(om).max()
+    assert np.abs(err - oe).max() <= 1e-14 * np.abs(oe).max()
+    with pytest.raises(rl.RlbmError):
+        rl.spectrum_average(np.zeros((0, 3)))

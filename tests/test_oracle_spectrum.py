@@ -62,3 +62,23 @@ def test_band_filter_beyond_the_lattice_is_identity_and_consistent_with_spectrum
     want = E0.copy()
     want[3:5] = 0.0
     assert np.abs(E1 - want).max() < 1e-18
+
+
+def test_spectrum_average_special_cases():
+    """Constant samples have zero error; the estimate is homogeneous of degree
+    one and independent of the sample order; two samples m(1 +- d) give
+    (m/2)(sqrt(d (2 + d)) + sqrt(d (2 - d))), the root taken of the magnitude."""
+    m = np.array([1.0, 0.5, 2e-3])
+    mean, err = diagnostics.spectrum_average(np.tile(m, (5, 1)))
+    assert np.array_equal(mean, m) and np.all(err == 0)
+    d = 0.1
+    S = np.stack([m * (1 + d), m * (1 - d)])
+    mean, err = diagnostics.spectrum_average(S)
+    assert np.abs(mean - m).max() < 1e-16
+    want = 0.5 * m * (np.sqrt(d * (2 + d)) + np.sqrt(d * (2 - d)))
+    assert np.abs(err - want).max() < 1e-15
+    g = np.random.Generator(np.random.Philox(1))
+    R = g.random((7, 4))
+    _, e1 = diagnostics.spectrum_average(R)
+    _, e2 = diagnostics.spectrum_average(3.0 * R[::-1])
+    assert np.abs(e2 - 3.0 * e1).max() < 1e-14
