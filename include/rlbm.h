@@ -78,7 +78,10 @@ enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_F16S = 2, RLBM_BF16S = 3 };
 /* ---- parameter blocks ----------------------------------------------------- */
 typedef struct {
     int32_t nx, ny;   /* lattice sites, 2 <= nx, ny <= 65536, periodic */
-    double  cfl;      /* c dt / dx in (0, 1]; a population moves cfl * v_q per step */
+    double  cfl;      /* c dt / dx in (0, 2]; a population moves cfl * v_q per step.
+                         cfl <= 1 reads the nearest nodes; 1 < cfl <= 2 (the paper's
+                         dt = 0.05 on its finest grid, spacing 0.04, is cfl 1.25)
+                         reads up to two nodes upstream, tile kernel form only */
 } rlbm_lattice;
 
 /* Stirring force (Sec. III C / Sec. V).  Driven modes: integer (kx, ky) with
@@ -127,7 +130,7 @@ int rlbm_workspace_bytes(const rlbm_lattice* lat, int stencil, int storage,
  * must stay valid until rlbm_destroy; hip_stream (hipStream_t, may be NULL
  * for the null stream) is where all work is enqueued.  The populations are
  * undefined until rlbm_set_state / rlbm_set_populations / rlbm_load.
- * Errors: EINVAL (bad lattice, tau <= 0.5, cfl outside (0, 1], k_lo > k_hi,
+ * Errors: EINVAL (bad lattice, tau <= 0.5, cfl outside (0, 2], k_lo > k_hi,
  * shell at or above Nyquist, unknown enum, null pointer), ENOSPACE, EHIP.  */
 int rlbm_init(rlbm_ctx** out, const rlbm_lattice* lat, double tau, int stencil,
               const rlbm_forcing* forcing, int storage,
@@ -241,7 +244,8 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                        from the lattice size and the GPU's resident waves).
  * By default the library picks RLBM_KERNEL_MARCH (param 0) for FP32 storage
  * when every resident wavefront gets a segment of at least 8 rows, and
- * RLBM_KERNEL_TILE with th = 4 otherwise.  rlbm_set_tile(th) is
+ * RLBM_KERNEL_TILE with th = 4 otherwise.  With cfl > 1 only the tile form
+ * exists (RLBM_KERNEL_MARCH gives EUNSUPPORTED).  rlbm_set_tile(th) is
  * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_autotune times the tile
  * heights and two segment lengths for `steps` steps each (advancing the
  * state) and keeps the fastest; *h_th receives th, or minus the segment

@@ -347,7 +347,8 @@ class Ensemble:
         self.n = len(self.sizes)
         self.device = torch.device(device)
         self.Q = len(stencil_info(stencil)[1])
-        lats = (_Lattice * self.n)(*[_lattice(nx, ny, cfl) for nx, ny in self.sizes])
+        cfls = list(cfl) if isinstance(cfl, (list, tuple)) else [cfl] * self.n
+        lats = (_Lattice * self.n)(*[_lattice(nx, ny, c) for (nx, ny), c in zip(self.sizes, cfls)])
         t = (ctypes.c_double * self.n)(*[float(x) for x in taus])
         fr = None
         if forcings is not None:

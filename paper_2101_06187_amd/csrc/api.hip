@@ -85,7 +85,7 @@ int validate_lattice(const rlbm_lattice* lat) {
     if (!lat) return fail(RLBM_EINVAL, "lattice is NULL");
     if (lat->nx < 2 || lat->ny < 2 || lat->nx > 65536 || lat->ny > 65536)
         return fail(RLBM_EINVAL, "lattice sides must be in [2, 65536]");
-    if (!(lat->cfl > 0.0 && lat->cfl <= 1.0)) return fail(RLBM_EINVAL, "cfl must be in (0, 1]");
+    if (!(lat->cfl > 0.0 && lat->cfl <= 2.0)) return fail(RLBM_EINVAL, "cfl must be in (0, 2]");
     return RLBM_OK;
 }
 
@@ -161,7 +161,8 @@ struct Engine {
     uint16_t* d_tiles = nullptr;
     uint16_t* d_gitems = nullptr;
     int n_gitems = 0;
-    bool unit_cfl = true, any_forced = false;
+    int smode = kStreamUnit;       // stream mode of the step kernel (all lattices)
+    bool any_forced = false;
     int th = 4, n_tiles = 0, grid = 0, cus = 0, tile_blocks = 0, extra_blocks = 0;
     int kind = kKernelTile, seglen_req = 0, seglen = 0;
     bool kind_auto = true;         // until rlbm_set_kernel / rlbm_set_tile / autotune
@@ -184,10 +185,10 @@ struct Engine {
 
     int occupancy() const {
         switch (storage) {
-            case RLBM_F64: return occ_f64(kind, stencil, unit_cfl, any_forced, th);
-            case RLBM_F32: return occ_f32(kind, stencil, unit_cfl, any_forced, th);
-            case RLBM_F16S: return occ_f16s(kind, stencil, unit_cfl, any_forced, th);
-            default: return occ_bf16s(kind, stencil, unit_cfl, any_forced, th);
+            case RLBM_F64: return occ_f64(kind, stencil, smode, any_forced, th);
+            case RLBM_F32: return occ_f32(kind, stencil, smode, any_forced, th);
+            case RLBM_F16S: return occ_f16s(kind, stencil, smode, any_forced, th);
+            default: return occ_bf16s(kind, stencil, smode, any_forced, th);
         }
     }
 
@@ -205,7 +206,8 @@ struct Engine {
         th = 4;
         const long long waves = (long long)cus * occupancy() * 4;
         const bool long_segments = wave_rows >= 8 * std::max(1LL, waves);
-        kind = (storage == RLBM_F32 && long_segments) ? kKernelMarch : kKernelTile;
+        kind = (storage == RLBM_F32 && long_segments && smode != kStreamHalo2) ? kKernelMarch
+                                                                                : kKernelTile;
     }
 
     int configure_tiles() {
@@ -304,7 +306,7 @@ struct Engine {
         L.args.th = th;
         L.args.tile_blocks = tile_blocks;
         L.stencil = stencil;
-        L.unit_cfl = unit_cfl;
+        L.smode = smode;
         L.forced = any_forced;
         L.grid = grid;
         L.stream = s;
@@ -454,7 +456,7 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
     E.d_tiles = (uint16_t*)(E.ws + E.lay.tiles);
     E.d_gitems = (uint16_t*)(E.ws + E.lay.gitems);
     E.hdesc.assign(n_real, RealDesc{});
-    E.unit_cfl = true;
+    E.smode = kStreamUnit;
     E.any_forced = false;
     const int s = storage_bytes(storage);
     for (int r = 0; r < n_real; ++r) {
@@ -487,7 +489,8 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         for (int i = 0; i < 3; ++i) d.af[i] = (float)d.a[i];
         d.dtf = (float)d.dt;
         d.inv_tauf = (float)d.inv_tau;
-        if (lat.cfl != 1.0) E.unit_cfl = false;
+        if (lat.cfl > 1.0) E.smode = kStreamHalo2;
+        else if (lat.cfl != 1.0 && E.smode == kStreamUnit) E.smode = kStreamGeneral;
         if (d.K >= 0) {
             E.any_forced = true;
         }
@@ -559,7 +562,9 @@ int engine_set_state(Engine& E, int r, const double* d_e, const double* d_ux,
 
 int engine_fields(Engine& E, int r, double* d_e, double* d_ux, double* d_uy, double* d_T,
                   double2* z) {
-    HIPCHK(launch_fields(E.d_desc, r, E.storage, E.stencil, E.lats[r].cfl == 1.0, E.lats[r].nx,
+    const double cfl = E.lats[r].cfl;
+    const int fmode = cfl > 1.0 ? kStreamHalo2 : (cfl == 1.0 ? kStreamUnit : kStreamGeneral);
+    HIPCHK(launch_fields(E.d_desc, r, E.storage, E.stencil, fmode, E.lats[r].nx,
                          E.lats[r].ny, E.parity(), d_e, d_ux, d_uy, d_T, z, E.d_flag, E.stream));
     return RLBM_OK;
 }
@@ -964,6 +969,8 @@ int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param) {
         E.th = param;
     } else if (kind == RLBM_KERNEL_MARCH) {
         if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
+        if (E.smode == kStreamHalo2)
+            return fail(RLBM_EUNSUPPORTED, "the row-marching form needs cfl <= 1");
         E.kind = kKernelMarch;
         E.seglen_req = param;
     } else {
@@ -993,6 +1000,7 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
     const int cand[6][2] = {{kKernelTile, 1}, {kKernelTile, 2}, {kKernelTile, 4}, {kKernelTile, 8},
                             {kKernelMarch, 0}, {kKernelMarch, -1}};
     for (const auto& c : cand) {
+        if (c[0] == kKernelMarch && E.smode == kStreamHalo2) continue;
         E.kind = c[0];
         if (c[0] == kKernelTile) E.th = c[1];
         else E.seglen_req = c[1] == 0 ? 0 : std::max(2, 2 * E.seglen);   // auto, then twice as long

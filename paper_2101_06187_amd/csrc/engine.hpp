@@ -64,11 +64,15 @@ struct StepArgs {
 
 enum { kKernelTile = 0, kKernelMarch = 1 };
 
+// Stream modes: general cfl <= 1; cfl == 1 (axis populations move exactly
+// one node); 1 < cfl <= 2 (sources up to two nodes upstream, tile form only).
+enum { kStreamGeneral = 0, kStreamUnit = 1, kStreamHalo2 = 2 };
+
 struct StepLaunch {
     StepArgs args;
     int kind;                     // kKernelTile or kKernelMarch
     int stencil;
-    bool unit_cfl;
+    int smode;                    // kStreamGeneral / kStreamUnit / kStreamHalo2
     bool forced;
     int grid;                     // persistent blocks
     hipStream_t stream;
@@ -82,10 +86,10 @@ hipError_t launch_step_f32(const StepLaunch& L);
 hipError_t launch_step_f16s(const StepLaunch& L);
 hipError_t launch_step_bf16s(const StepLaunch& L);
 // Resident blocks per CU of a step-kernel configuration (occupancy query).
-int occ_f64(int kind, int stencil, bool unit_cfl, bool forced, int th);
-int occ_f32(int kind, int stencil, bool unit_cfl, bool forced, int th);
-int occ_f16s(int kind, int stencil, bool unit_cfl, bool forced, int th);
-int occ_bf16s(int kind, int stencil, bool unit_cfl, bool forced, int th);
+int occ_f64(int kind, int stencil, int smode, bool forced, int th);
+int occ_f32(int kind, int stencil, int smode, bool forced, int th);
+int occ_f16s(int kind, int stencil, int smode, bool forced, int th);
+int occ_bf16s(int kind, int stencil, int smode, bool forced, int th);
 
 // Force table of the current step (kernels_aux.hip), for initial states.
 hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s);
@@ -101,7 +105,7 @@ hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, in
                                   int nx, int ny, double* out, int parity,
                                   hipStream_t s);
 hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil,
-                         bool unit_cfl, int nx, int ny, int parity, double* e,
+                         int smode, int nx, int ny, int parity, double* e,
                          double* ux, double* uy, double* T, double2* z,
                          int* d_flag, hipStream_t s);
 hipError_t launch_conserved(const RealDesc* d_desc, int r, int storage, int stencil,

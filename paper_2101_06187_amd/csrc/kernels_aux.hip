@@ -105,7 +105,7 @@ __global__ void get_pop_kernel(const RealDesc* desc, int r, double* out, int par
 // fields: stage (c) of the step in FP64 -- stream the current populations,
 // form T^{mu nu}, solve the Landau frame.
 // ---------------------------------------------------------------------------
-template <class S, class St, bool UNIT>
+template <class S, class St, int SM>
 __global__ void fields_kernel(const RealDesc* desc, int r, int parity, double* e, double* ux,
                               double* uy, double* T, double2* z, int* d_flag) {
     const RealDesc& D = desc[r];
@@ -118,14 +118,29 @@ __global__ void fields_kernel(const RealDesc* desc, int r, int parity, double* e
     const long long plane_bytes = (long long)D.pitch * sizeof(typename S::raw);
     const long long rowq = plane_bytes * St::Q;
     const char* src = (const char*)uni(D.buf[parity]);
-    const char* const rows[3] = {src + ym * rowq, src + y * rowq, src + yp * rowq};
-    const uint32_t cols[3] = {(uint32_t)(xm * sizeof(typename S::raw)),
-                              (uint32_t)(x * sizeof(typename S::raw)),
-                              (uint32_t)(xp * sizeof(typename S::raw))};
-    InterpW<double> W;
-    W.set(D.a[0], D.a[1], D.a[2]);
     double f[St::Q];
-    stream_pull<S, St, UNIT, double>(rows, plane_bytes, cols, W, f);
+    if constexpr (SM == kStreamHalo2) {
+        auto wrap = [](int v, int n) { return v < 0 ? (v + n < 0 ? v + 2 * n : v + n)
+                                                    : (v >= n ? (v - n >= n ? v - 2 * n : v - n) : v); };
+        const char* rows5[5];
+        uint32_t cols5[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            rows5[j] = src + (long long)wrap(y + j - 2, ny) * rowq;
+            cols5[j] = (uint32_t)(wrap(x + j - 2, nx) * sizeof(typename S::raw));
+        }
+        InterpW2<double> W2;
+        W2.set(D.a[0], D.a[1], D.a[2]);
+        stream_pull_h2<S, St, double>(rows5, plane_bytes, cols5, W2, f);
+    } else {
+        const char* const rows[3] = {src + ym * rowq, src + y * rowq, src + yp * rowq};
+        const uint32_t cols[3] = {(uint32_t)(xm * sizeof(typename S::raw)),
+                                  (uint32_t)(x * sizeof(typename S::raw)),
+                                  (uint32_t)(xp * sizeof(typename S::raw))};
+        InterpW<double> W;
+        W.set(D.a[0], D.a[1], D.a[2]);
+        stream_pull<S, St, SM, double>(rows, plane_bytes, cols, W, f);
+    }
     const Moments<double> m = moments<St, false>(f);
     const double sh = (double)S::shift;
     const double E = m.E + sh, Pxx = m.Pxx + sh / St::D, Pyy = m.Pyy + sh / St::D;
@@ -445,16 +460,19 @@ struct GetPopFn {
 };
 template <class S, class St>
 struct FieldsFn {
-    static hipError_t run(const RealDesc* d, int r, bool unit, int nx, int ny, int parity,
+    static hipError_t run(const RealDesc* d, int r, int smode, int nx, int ny, int parity,
                           double* e, double* ux, double* uy, double* T, double2* z, int* flag,
                           hipStream_t s) {
         const dim3 g((nx + 127) / 128, ny), b(128);
-        if (unit)
-            hipLaunchKernelGGL((fields_kernel<S, St, true>), g, b, 0, s, d, r, parity, e, ux, uy, T,
-                               z, flag);
+        if (smode == kStreamUnit)
+            hipLaunchKernelGGL((fields_kernel<S, St, kStreamUnit>), g, b, 0, s, d, r, parity, e, ux,
+                               uy, T, z, flag);
+        else if (smode == kStreamHalo2)
+            hipLaunchKernelGGL((fields_kernel<S, St, kStreamHalo2>), g, b, 0, s, d, r, parity, e, ux,
+                               uy, T, z, flag);
         else
-            hipLaunchKernelGGL((fields_kernel<S, St, false>), g, b, 0, s, d, r, parity, e, ux, uy,
-                               T, z, flag);
+            hipLaunchKernelGGL((fields_kernel<S, St, kStreamGeneral>), g, b, 0, s, d, r, parity, e,
+                               ux, uy, T, z, flag);
         return hipGetLastError();
     }
 };
@@ -483,10 +501,10 @@ hipError_t launch_get_populations(const RealDesc* d_desc, int r, int storage, in
                                   int nx, int ny, double* out, int parity, hipStream_t s) {
     return dispatch<GetPopFn>(storage, stencil, d_desc, r, nx, ny, out, parity, s);
 }
-hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil, bool unit_cfl,
+hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil, int smode,
                          int nx, int ny, int parity, double* e, double* ux, double* uy,
                          double* T, double2* z, int* d_flag, hipStream_t s) {
-    return dispatch<FieldsFn>(storage, stencil, d_desc, r, unit_cfl, nx, ny, parity, e, ux, uy,
+    return dispatch<FieldsFn>(storage, stencil, d_desc, r, smode, nx, ny, parity, e, ux, uy,
                               T, z, d_flag, s);
 }
 hipError_t launch_conserved(const RealDesc* d_desc, int r, int storage, int stencil, int nx,

@@ -32,7 +32,7 @@ using Store = StF16S;
 using Store = StBF16S;
 #endif
 
-template <class S, class St, bool UNIT, bool FORCED>
+template <class S, class St, int SM, bool FORCED>
 __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     using T = typename S::T;
     using raw = typename S::raw;
@@ -61,6 +61,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     const char* src = nullptr;
     char* dst = nullptr;
     InterpW<T> W;
+    InterpW2<T> W2;
     T ginv = 0, dt = 0;
     int eta_s = 0;
     const T* twp = nullptr;
@@ -81,11 +82,13 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             src = (const char*)uni(Dsc.buf[par]);
             dst = (char*)uni(Dsc.buf[par ^ 1]);
             if constexpr (F64) {
-                W.set(uni(Dsc.a[0]), uni(Dsc.a[1]), uni(Dsc.a[2]));
+                if constexpr (SM == kStreamHalo2) W2.set(uni(Dsc.a[0]), uni(Dsc.a[1]), uni(Dsc.a[2]));
+                else W.set(uni(Dsc.a[0]), uni(Dsc.a[1]), uni(Dsc.a[2]));
                 ginv = uni(Dsc.inv_tau);
                 dt = uni(Dsc.dt);
             } else {
-                W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
+                if constexpr (SM == kStreamHalo2) W2.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
+                else W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
                 ginv = uni(Dsc.inv_tauf);
                 dt = uni(Dsc.dtf);
             }
@@ -115,18 +118,31 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
         const int y = uni(tyi * A.th + ly);          // one tile row per wavefront
         if (x >= nx || y >= ny) continue;
 
-        const int xm = x == 0 ? nx - 1 : x - 1;
-        const int xp = x == nx - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? ny - 1 : y - 1;
-        const int yp = y == ny - 1 ? 0 : y + 1;
-        const char* const rows[3] = {src + ym * rowq_bytes, src + y * rowq_bytes,
-                                     src + yp * rowq_bytes};
-        const uint32_t cols[3] = {(uint32_t)(xm * sizeof(raw)), (uint32_t)(x * sizeof(raw)),
-                                  (uint32_t)(xp * sizeof(raw))};
-
         // (b) stream
         T f[St::Q];
-        stream_pull<S, St, UNIT>(rows, plane_bytes, cols, W, f);
+        if constexpr (SM == kStreamHalo2) {
+            // rows y-2 .. y+2 and columns x-2 .. x+2, periodic (nx, ny >= 2)
+            auto wrap = [](int v, int n) { return v < 0 ? (v + n < 0 ? v + 2 * n : v + n)
+                                                        : (v >= n ? (v - n >= n ? v - 2 * n : v - n) : v); };
+            const char* rows5[5];
+            uint32_t cols5[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                rows5[j] = src + (long long)uni(wrap(y + j - 2, ny)) * rowq_bytes;
+                cols5[j] = (uint32_t)(wrap(x + j - 2, nx) * sizeof(raw));
+            }
+            stream_pull_h2<S, St>(rows5, plane_bytes, cols5, W2, f);
+        } else {
+            const int xm = x == 0 ? nx - 1 : x - 1;
+            const int xp = x == nx - 1 ? 0 : x + 1;
+            const int ym = y == 0 ? ny - 1 : y - 1;
+            const int yp = y == ny - 1 ? 0 : y + 1;
+            const char* const rows[3] = {src + ym * rowq_bytes, src + y * rowq_bytes,
+                                         src + yp * rowq_bytes};
+            const uint32_t cols[3] = {(uint32_t)(xm * sizeof(raw)), (uint32_t)(x * sizeof(raw)),
+                                      (uint32_t)(xp * sizeof(raw))};
+            stream_pull<S, St, SM>(rows, plane_bytes, cols, W, f);
+        }
 
         const SiteCtx<T> sctx{ginv, dt, K, gtab, plane_bytes, eta_s};
         T c1 = 0, s1 = 0;
@@ -137,7 +153,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
                 s1 = twx[2 * x + 1];
             }
         }
-        update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), cols[1],
+        update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), (uint32_t)(x * sizeof(raw)),
                                    A.d_flag);
     }
 
@@ -243,8 +259,10 @@ __device__ __forceinline__ T write_lane(T old, T val, int lane) {
     return (int)threadIdx.x == lane ? val : old;
 }
 
-template <class S, class St, bool UNIT, bool FORCED>
+template <class S, class St, int SM, bool FORCED>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
+    static_assert(SM != kStreamHalo2, "the row-marching form streams from the nearest rows only");
+    constexpr bool UNIT = SM == kStreamUnit;
     using T = typename S::T;
     using raw = typename S::raw;
     using M = MarchMap<St>;
@@ -431,23 +449,33 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
     }
 }
 
-template <class St, bool UNIT, bool FORCED>
+template <class St, int SM, bool FORCED>
 static const void* kernel_ptr(int kind) {
-    if (kind == kKernelMarch) return (const void*)march_kernel<Store, St, UNIT, FORCED>;
-    return (const void*)step_kernel<Store, St, UNIT, FORCED>;
+    if constexpr (SM == kStreamHalo2) {
+        // cfl > 1: tile form only
+        return kind == kKernelMarch ? nullptr : (const void*)step_kernel<Store, St, SM, FORCED>;
+    } else {
+        if (kind == kKernelMarch) return (const void*)march_kernel<Store, St, SM, FORCED>;
+        return (const void*)step_kernel<Store, St, SM, FORCED>;
+    }
 }
 
-static const void* select_kernel(int kind, int stencil, bool unit, bool forced) {
-    if (stencil == RLBM_STENCIL_SPH26) {
-        if (unit) return forced ? kernel_ptr<Sph26, true, true>(kind) : kernel_ptr<Sph26, true, false>(kind);
-        return forced ? kernel_ptr<Sph26, false, true>(kind) : kernel_ptr<Sph26, false, false>(kind);
+template <class St>
+static const void* kernel_for(int kind, int smode, bool forced) {
+    switch (smode) {
+        case kStreamUnit:
+            return forced ? kernel_ptr<St, kStreamUnit, true>(kind) : kernel_ptr<St, kStreamUnit, false>(kind);
+        case kStreamHalo2:
+            return forced ? kernel_ptr<St, kStreamHalo2, true>(kind) : kernel_ptr<St, kStreamHalo2, false>(kind);
+        default:
+            return forced ? kernel_ptr<St, kStreamGeneral, true>(kind) : kernel_ptr<St, kStreamGeneral, false>(kind);
     }
-    if (stencil == RLBM_STENCIL_SPH26_ZFOLD) {
-        if (unit) return forced ? kernel_ptr<Sph17, true, true>(kind) : kernel_ptr<Sph17, true, false>(kind);
-        return forced ? kernel_ptr<Sph17, false, true>(kind) : kernel_ptr<Sph17, false, false>(kind);
-    }
-    if (unit) return forced ? kernel_ptr<Circ8, true, true>(kind) : kernel_ptr<Circ8, true, false>(kind);
-    return forced ? kernel_ptr<Circ8, false, true>(kind) : kernel_ptr<Circ8, false, false>(kind);
+}
+
+static const void* select_kernel(int kind, int stencil, int smode, bool forced) {
+    if (stencil == RLBM_STENCIL_SPH26) return kernel_for<Sph26>(kind, smode, forced);
+    if (stencil == RLBM_STENCIL_SPH26_ZFOLD) return kernel_for<Sph17>(kind, smode, forced);
+    return kernel_for<Circ8>(kind, smode, forced);
 }
 
 #if RLBM_STORAGE_ID == 0
@@ -465,7 +493,8 @@ static const void* select_kernel(int kind, int stencil, bool unit, bool forced) 
 #endif
 
 hipError_t RLBM_LAUNCH_NAME(const StepLaunch& L) {
-    const void* k = select_kernel(L.kind, L.stencil, L.unit_cfl, L.forced);
+    const void* k = select_kernel(L.kind, L.stencil, L.smode, L.forced);
+    if (!k) return hipErrorInvalidDeviceFunction;
     StepArgs a = L.args;
     void* params[] = {&a};
     if (L.ev_start)
@@ -474,9 +503,10 @@ hipError_t RLBM_LAUNCH_NAME(const StepLaunch& L) {
     return hipLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, 0, L.stream);
 }
 
-int RLBM_OCC_NAME(int kind, int stencil, bool unit, bool forced, int th) {
+int RLBM_OCC_NAME(int kind, int stencil, int smode, bool forced, int th) {
     int blocks = 0;
-    const void* k = select_kernel(kind, stencil, unit, forced);
+    const void* k = select_kernel(kind, stencil, smode, forced);
+    if (!k) return 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kTileW * th, 0) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;

@@ -131,10 +131,11 @@ struct InterpW {
     }
 };
 
-template <class S, class St, bool UNIT, class T>
+template <class S, class St, int SM, class T>
 __device__ __forceinline__ void stream_pull(const char* const (&rows)[3], long long plane_bytes,
                                             const uint32_t (&cols)[3], const InterpW<T>& W,
                                             T (&f)[St::Q]) {
+    constexpr bool UNIT = SM == kStreamUnit;
     using raw = typename S::raw;
     sfor<0, St::Q>([&](auto iq) {
         constexpr int q = decltype(iq)::value;
@@ -156,6 +157,64 @@ __device__ __forceinline__ void stream_pull(const char* const (&rows)[3], long l
         } else {
             const T s = L(1, ux) + L(uy, 1);
             f[q] = fma(W.w11[n - 1], L(uy, ux), fma(W.w10[n - 1], s, W.w00[n - 1] * L(1, 1)));
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// 1 < cfl <= 2.  A population with displacement a = cfl |v_x| along x comes
+// from between the nodes floor(a) and floor(a) + 1 upstream; with the 1-D
+// weights of the upstream offsets 0, 1, 2
+//   a <= 1: (1 - a, a, 0),   1 < a <= 2: (0, 2 - a, a - 1),
+// the interpolant is sum_k c_k F(x - k sign(c_x)), and for c_x, c_y both
+// non-zero (|v_x| = |v_y|) the tensor product sum_{i,j} c_i c_j F(x - i, y - j).
+// rows[j] is the row y + j - 2, cols[i] the column x + i - 2.
+// ---------------------------------------------------------------------------
+template <class T>
+struct InterpW2 {
+    T c[3][3];    // [n - 1][offset]: 1-D weights for 1, 2, 3 non-zero components
+    __device__ void set(T a1, T a2, T a3) {
+        const T a[3] = {a1, a2, a3};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const bool far = a[i] > (T)1;
+            c[i][0] = far ? (T)0 : (T)1 - a[i];
+            c[i][1] = far ? (T)2 - a[i] : a[i];
+            c[i][2] = far ? a[i] - (T)1 : (T)0;
+        }
+    }
+};
+
+template <class S, class St, class T>
+__device__ __forceinline__ void stream_pull_h2(const char* const (&rows)[5], long long plane_bytes,
+                                               const uint32_t (&cols)[5], const InterpW2<T>& W,
+                                               T (&f)[St::Q]) {
+    using raw = typename S::raw;
+    sfor<0, St::Q>([&](auto iq) {
+        constexpr int q = decltype(iq)::value;
+        constexpr Dir d = St::dir[q];
+        constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+        constexpr int sx = d.cx > 0 ? -1 : (d.cx < 0 ? 1 : 0);   // column step upstream
+        constexpr int sy = d.cy > 0 ? -1 : (d.cy < 0 ? 1 : 0);   // row step upstream
+        auto L = [&](int j, int i) -> T {                        // j rows, i columns upstream
+            return (T)S::ld((gp<const raw>)(rows[2 + sy * j] + (long long)q * plane_bytes +
+                                            cols[2 + sx * i]));
+        };
+        const T* c = W.c[n > 0 ? n - 1 : 0];
+        if constexpr (d.cx == 0 && d.cy == 0) {
+            f[q] = L(0, 0);
+        } else if constexpr (d.cy == 0) {
+            f[q] = fma(c[2], L(0, 2), fma(c[1], L(0, 1), c[0] * L(0, 0)));
+        } else if constexpr (d.cx == 0) {
+            f[q] = fma(c[2], L(2, 0), fma(c[1], L(1, 0), c[0] * L(0, 0)));
+        } else {
+            T acc = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const T r = fma(c[2], L(j, 2), fma(c[1], L(j, 1), c[0] * L(j, 0)));
+                acc = fma(c[j], r, acc);
+            }
+            f[q] = acc;
         }
     });
 }

@@ -130,7 +130,7 @@ def _init(**kw):
                        args["ws_bytes"], None)
 
 
-@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(cfl=0.0), dict(cfl=1.5),
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(cfl=0.0), dict(cfl=2.5),
                                 dict(nx=1), dict(ny=0), dict(stencil=7), dict(storage=9),
                                 dict(ws=0), dict(ws=257)])
 def test_init_rejects_invalid_arguments(kw):

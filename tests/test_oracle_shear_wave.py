@@ -68,3 +68,19 @@ def test_shear_wave_decay_matches_linear_theory(sph26):
     assert np.abs(ux - ux[:, :1]).max() < 1e-15
     assert np.abs(uy - uy[:, :1]).max() < 1e-15
     assert np.abs(uy).max() < 1e-2 * 0.01 ** 2
+
+
+@pytest.mark.parametrize("cfl", [0.8, 1.25])
+def test_shear_wave_decay_matches_linear_theory_other_cfl(sph26, cfl):
+    """The same check with the pull displacement below one node and above it
+    (sources up to two nodes upstream)."""
+    n, tau = 32, 0.8
+    lam = abs(shear_eigenvalue(sph26, tau, 2 * np.pi / n, cfl))
+    e, bx, by = workloads.shear_wave(n, 0.01)
+    F = rlbm.set_state(e, bx, by, sph26)
+    F = rlbm.run(F, sph26, tau, 60, cfl=cfl)
+    a0 = np.abs(np.fft.rfft(diagnostics.fields(F, sph26, cfl)[1][:, 0])[1])
+    F = rlbm.run(F, sph26, tau, 120, cfl=cfl)
+    a1 = np.abs(np.fft.rfft(diagnostics.fields(F, sph26, cfl)[1][:, 0])[1])
+    rate = (a1 / a0) ** (1 / 120)
+    assert abs(rate / lam - 1) < 1e-6

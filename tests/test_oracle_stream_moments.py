@@ -32,7 +32,7 @@ def brute_stream(F, v, cfl):
 
 
 @pytest.mark.parametrize("shape", [(3, 3), (3, 5), (4, 4), (6, 5)])
-@pytest.mark.parametrize("cfl", [1.0, 0.7, 0.35])
+@pytest.mark.parametrize("cfl", [1.0, 0.7, 0.35, 1.25, 1.6, 2.0])
 def test_stream_brute_force(sph26, shape, cfl):
     ny, nx = shape
     F = workloads.random_populations(sph26.v, ny, nx, seed=ny * 10 + nx)
