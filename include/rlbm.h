@@ -120,7 +120,8 @@ int rlbm_forcing_modes(const rlbm_lattice* lat, const rlbm_forcing* forcing,
 /* ---- one lattice ------------------------------------------------------------ */
 
 /* Bytes of device workspace rlbm_init needs (two population buffers of
- * Q * ny * pitch elements plus forcing tables and a few KB of control data).
+ * Q * ny * pitch elements, pitch = nx rounded up to 64, plus forcing tables
+ * and a few KB of control data).
  * forcing may be NULL (unforced).                                          */
 int rlbm_workspace_bytes(const rlbm_lattice* lat, int stencil, int storage,
                          const rlbm_forcing* forcing, size_t* h_bytes);
@@ -227,8 +228,11 @@ int rlbm_spectrum_average(const double* h_samples, int32_t n_samples, int32_t nb
                           double* h_mean, double* h_err);
 
 /* Checkpoint: a self-describing host blob (header: lattice, stencil,
- * storage, tau and relaxation mode, forcing, step counter; then the populations in the storage
- * type).  A run resumed from it continues bit for bit, because the forcing
+ * storage, tau and relaxation mode, forcing, step counter; then the
+ * population buffer as the library stores it, in the storage type: rows of
+ * Q * pitch elements, pitch = nx rounded up to 64, each row made of 64-column
+ * bricks holding population 0 .. Q-1 in turn; the padding columns carry no
+ * data).  A run resumed from it continues bit for bit, because the forcing
  * is counter-based.  rlbm_load rejects a blob of another configuration
  * (EINVAL).  Both synchronise.                                             */
 int rlbm_state_bytes(const rlbm_ctx* ctx, size_t* h_bytes);

@@ -879,7 +879,7 @@ int rlbm_state_bytes(const rlbm_ctx* ctx, size_t* h_bytes) {
     if (!h_bytes) return fail(RLBM_EINVAL, "NULL output");
     const Engine& E = ctx->e;
     *h_bytes = sizeof(SaveHeader) +
-               (size_t)E.Q * E.lats[0].nx * E.lats[0].ny * storage_bytes(E.storage);
+               (size_t)E.Q * E.hdesc[0].pitch * E.lats[0].ny * storage_bytes(E.storage);
     return RLBM_OK;
 }
 
@@ -907,14 +907,11 @@ int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes) {
     h.k_hi = E.frc[0].k_hi;
     h.seed = E.frc[0].seed;
     std::memcpy(h_buf, &h, sizeof(h));
-    const int s = storage_bytes(E.storage);
+    // the population buffer as stored (row bricks, padded columns included)
     const RealDesc& d = E.hdesc[0];
     char* dst = (char*)h_buf + sizeof(h);
-    for (int q = 0; q < E.Q; ++q)   // population q: rows (q + y Q) * pitch apart
-        HIPCHK(hipMemcpy2DAsync(dst + (size_t)q * d.nx * d.ny * s, (size_t)d.nx * s,
-                                (const char*)d.buf[E.parity()] + (size_t)q * d.pitch * s,
-                                (size_t)d.pitch * E.Q * s, (size_t)d.nx * s, d.ny,
-                                hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipMemcpyAsync(dst, d.buf[E.parity()], need - sizeof(h), hipMemcpyDeviceToHost,
+                          E.stream));
     HIPCHK(hipStreamSynchronize(E.stream));
     return RLBM_OK;
 }
@@ -936,14 +933,10 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
         return fail(RLBM_EINVAL, "checkpoint of another configuration");
     E.step = h.step;
     HIPCHK(launch_reset(E.d_step, h.step, E.d_flag, E.stream));
-    const int s = storage_bytes(E.storage);
     const RealDesc& d = E.hdesc[0];
     const char* src = (const char*)h_buf + sizeof(h);
-    for (int q = 0; q < E.Q; ++q)
-        HIPCHK(hipMemcpy2DAsync((char*)d.buf[E.parity()] + (size_t)q * d.pitch * s,
-                                (size_t)d.pitch * E.Q * s, src + (size_t)q * d.nx * d.ny * s,
-                                (size_t)d.nx * s, (size_t)d.nx * s, d.ny, hipMemcpyHostToDevice,
-                                E.stream));
+    HIPCHK(hipMemcpyAsync(d.buf[E.parity()], src, need - sizeof(h), hipMemcpyHostToDevice,
+                          E.stream));
     if (int rc = E.prime_force_table()) return rc;
     HIPCHK(hipStreamSynchronize(E.stream));
     return RLBM_OK;

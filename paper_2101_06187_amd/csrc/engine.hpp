@@ -25,8 +25,7 @@ struct RealDesc {
     const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
     const int* kptr;              // K+2 offsets into modes
     int nx, ny;
-    int pitch;                    // elements per population row; element (q, y, x)
-                                  // is at (y * Q + q) * pitch + x (row-interleaved)
+    int pitch;                    // nx rounded up to 64; see pop_index for the layout
     int tiles_x, tiles_y;
     int tile_begin;               // first work item (tile or strip segment) of this lattice
     int seglen;                   // rows per strip segment (marching kernel)
@@ -61,6 +60,21 @@ struct StepArgs {
     int tile_blocks;              // blocks [0, tile_blocks) walk the tiles; any further
                                   // blocks only build the next force table
 };
+
+// Population layout in HBM ("row bricks").  Lattice row y is one contiguous
+// block of Q * pitch elements (pitch = nx rounded up to 64) made of pitch / 64
+// bricks; brick b holds columns [64 b, 64 b + 64): the 64 values of
+// population 0, then those of population 1, and so on.  A wavefront's 64
+// sites of one row thus read population q at a fixed offset q * 64 elements
+// from the brick, which the load instructions carry as an immediate.
+__host__ __device__ inline long long pop_index(int q, int y, int x, int Q, int pitch) {
+    return (long long)y * Q * pitch + (long long)(x >> 6) * (Q * kTileW) + q * kTileW + (x & 63);
+}
+// byte offset of column x inside a row (same for every population)
+template <class Raw>
+__host__ __device__ inline uint32_t col_bytes(int x, int Q) {
+    return (uint32_t)(((x >> 6) * (Q * kTileW) + (x & 63)) * (int)sizeof(Raw));
+}
 
 enum { kKernelTile = 0, kKernelMarch = 1 };
 

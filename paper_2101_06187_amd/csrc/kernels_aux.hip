@@ -73,7 +73,7 @@ __global__ void set_state_kernel(const RealDesc* desc, int r, const double* e,
         constexpr double vx = dir_comp(St::dir[q], 0), vy = dir_comp(St::dir[q], 1);
         const double t = vx * bx + vy * by;
         const double F = fma(C, t * t, fma(B, t, A0));
-        dst[((long long)y * St::Q + q) * D.pitch + x] = S::from64(F - S::shift);
+        dst[pop_index(q, y, x, St::Q, D.pitch)] = S::from64(F - S::shift);
     });
 }
 
@@ -85,7 +85,7 @@ __global__ void set_pop_kernel(const RealDesc* desc, int r, const double* in, in
     if (x >= D.nx) return;
     typename S::raw* dst = (typename S::raw*)D.buf[parity];
     for (int q = 0; q < St::Q; ++q)
-        dst[((long long)y * St::Q + q) * D.pitch + x] =
+        dst[pop_index(q, y, x, St::Q, D.pitch)] =
             S::from64(in[((long long)q * D.ny + y) * D.nx + x] - S::shift);
 }
 
@@ -98,7 +98,7 @@ __global__ void get_pop_kernel(const RealDesc* desc, int r, double* out, int par
     const typename S::raw* src = (const typename S::raw*)D.buf[parity];
     for (int q = 0; q < St::Q; ++q)
         out[((long long)q * D.ny + y) * D.nx + x] =
-            S::to64(src[((long long)y * St::Q + q) * D.pitch + x]) + S::shift;
+            S::to64(src[pop_index(q, y, x, St::Q, D.pitch)]) + S::shift;
 }
 
 // ---------------------------------------------------------------------------
@@ -115,8 +115,7 @@ __global__ void fields_kernel(const RealDesc* desc, int r, int parity, double* e
     const int nx = D.nx, ny = D.ny;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const long long plane_bytes = (long long)D.pitch * sizeof(typename S::raw);
-    const long long rowq = plane_bytes * St::Q;
+    const long long rowq = (long long)D.pitch * St::Q * (long long)sizeof(typename S::raw);
     const char* src = (const char*)uni(D.buf[parity]);
     double f[St::Q];
     if constexpr (SM == kStreamHalo2) {
@@ -127,19 +126,19 @@ __global__ void fields_kernel(const RealDesc* desc, int r, int parity, double* e
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             rows5[j] = src + (long long)wrap(y + j - 2, ny) * rowq;
-            cols5[j] = (uint32_t)(wrap(x + j - 2, nx) * sizeof(typename S::raw));
+            cols5[j] = col_bytes<typename S::raw>(wrap(x + j - 2, nx), St::Q);
         }
         InterpW2<double> W2;
         W2.set(D.a[0], D.a[1], D.a[2]);
-        stream_pull_h2<S, St, double>(rows5, plane_bytes, cols5, W2, f);
+        stream_pull_h2<S, St, double>(rows5, cols5, W2, f);
     } else {
         const char* const rows[3] = {src + ym * rowq, src + y * rowq, src + yp * rowq};
-        const uint32_t cols[3] = {(uint32_t)(xm * sizeof(typename S::raw)),
-                                  (uint32_t)(x * sizeof(typename S::raw)),
-                                  (uint32_t)(xp * sizeof(typename S::raw))};
+        const uint32_t cols[3] = {col_bytes<typename S::raw>(xm, St::Q),
+                                  col_bytes<typename S::raw>(x, St::Q),
+                                  col_bytes<typename S::raw>(xp, St::Q)};
         InterpW<double> W;
         W.set(D.a[0], D.a[1], D.a[2]);
-        stream_pull<S, St, SM, double>(rows, plane_bytes, cols, W, f);
+        stream_pull<S, St, SM, double>(rows, cols, W, f);
     }
     const Moments<double> m = moments<St, false>(f);
     const double sh = (double)S::shift;
@@ -208,7 +207,7 @@ conserved_kernel(const RealDesc* desc, int r, int parity, double* partials) {
         const int y = (int)(i / D.nx), x = (int)(i - (long long)y * D.nx);
         double f[St::Q];
         for (int q = 0; q < St::Q; ++q)
-            f[q] = S::to64(src[((long long)y * St::Q + q) * D.pitch + x]);
+            f[q] = S::to64(src[pop_index(q, y, x, St::Q, D.pitch)]);
         const Moments<double> m = moments<St, false>(f);
         acc[0] += m.E + (double)S::shift;
         acc[1] += m.Jx;

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     int cur_r = -1;
     int nx = 0, ny = 0, tiles_x = 1, tile_begin = 0, K = -1;
     int dq = 0, dr = 0;                      // nb = dq * tiles_x + dr
-    long long rowq_bytes = 0, plane_bytes = 0;
+    long long rowq_bytes = 0;
     const char* src = nullptr;
     char* dst = nullptr;
     InterpW<T> W;
@@ -77,8 +77,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             tiles_x = uni(Dsc.tiles_x);
             tile_begin = uni(Dsc.tile_begin);
             const int pitch = uni(Dsc.pitch);
-            plane_bytes = (long long)pitch * (long long)sizeof(raw);
-            rowq_bytes = plane_bytes * St::Q;
+            rowq_bytes = (long long)pitch * St::Q * (long long)sizeof(raw);
             src = (const char*)uni(Dsc.buf[par]);
             dst = (char*)uni(Dsc.buf[par ^ 1]);
             if constexpr (F64) {
@@ -129,9 +128,9 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
 #pragma unroll
             for (int j = 0; j < 5; ++j) {
                 rows5[j] = src + (long long)uni(wrap(y + j - 2, ny)) * rowq_bytes;
-                cols5[j] = (uint32_t)(wrap(x + j - 2, nx) * sizeof(raw));
+                cols5[j] = col_bytes<raw>(wrap(x + j - 2, nx), St::Q);
             }
-            stream_pull_h2<S, St>(rows5, plane_bytes, cols5, W2, f);
+            stream_pull_h2<S, St>(rows5, cols5, W2, f);
         } else {
             const int xm = x == 0 ? nx - 1 : x - 1;
             const int xp = x == nx - 1 ? 0 : x + 1;
@@ -139,12 +138,12 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             const int yp = y == ny - 1 ? 0 : y + 1;
             const char* const rows[3] = {src + ym * rowq_bytes, src + y * rowq_bytes,
                                          src + yp * rowq_bytes};
-            const uint32_t cols[3] = {(uint32_t)(xm * sizeof(raw)), (uint32_t)(x * sizeof(raw)),
-                                      (uint32_t)(xp * sizeof(raw))};
-            stream_pull<S, St, SM>(rows, plane_bytes, cols, W, f);
+            const uint32_t cols[3] = {col_bytes<raw>(xm, St::Q), col_bytes<raw>(x, St::Q),
+                                      col_bytes<raw>(xp, St::Q)};
+            stream_pull<S, St, SM>(rows, cols, W, f);
         }
 
-        const SiteCtx<T> sctx{ginv, dt, K, gtab, plane_bytes, eta_s};
+        const SiteCtx<T> sctx{ginv, dt, K, gtab, eta_s};
         T c1 = 0, s1 = 0;
         if constexpr (FORCED) {
             if (K >= 0) {
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
                 s1 = twx[2 * x + 1];
             }
         }
-        update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), (uint32_t)(x * sizeof(raw)),
+        update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), col_bytes<raw>(x, St::Q),
                                    A.d_flag);
     }
 
@@ -302,8 +301,8 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
         const int R = min(kTileW - 1, nx - 1 - x0);      // last active lane
         const int x = x0 + lane;
         const bool active = lane <= R;
-        const long long plane_bytes = (long long)uni(Dsc.pitch) * (long long)sizeof(raw);
-        const long long rowq = plane_bytes * Q;
+        constexpr long long plane_bytes = kTileW * sizeof(raw);
+        const long long rowq = (long long)uni(Dsc.pitch) * Q * (long long)sizeof(raw);
         const char* src = (const char*)uni(Dsc.buf[par]);
         char* dst = (char*)uni(Dsc.buf[par ^ 1]);
         InterpW<T> W;
@@ -317,7 +316,6 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
             sctx.ginv = uni(Dsc.inv_tauf);
             sctx.dt = uni(Dsc.dtf);
         }
-        sctx.plane_bytes = plane_bytes;
         sctx.K = -1;
         sctx.eta_s = uni(Dsc.tau_mode);
         sctx.gtab = nullptr;
@@ -331,7 +329,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
                 s1 = twx[2 * x + 1];
             }
         }
-        const uint32_t colb = (uint32_t)(x * sizeof(raw));
+        const uint32_t colb = col_bytes<raw>(x, Q);
         auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
         auto ld = [&](int q, int yy) -> T {
             const char* rowp = src + (long long)wrap(yy) * rowq + (long long)q * plane_bytes;
@@ -356,7 +354,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
             T h = 0;
             if (lane < NH) {
                 const char* p = src + (long long)wrap(yy + my_dy) * rowq +
-                                (long long)my_q * plane_bytes + (long long)hcol * sizeof(raw);
+                                (long long)my_q * plane_bytes + col_bytes<raw>(hcol, Q);
                 h = (T)S::ld((gp<const raw>)p);
             }
             return h;

@@ -102,11 +102,10 @@ struct StBF16S {
 
 // ---------------------------------------------------------------------------
 // pull streaming by linear interpolation (Sec. III B), periodic lattice.
-// Populations are stored row-interleaved: element (q, y, x) at
-// (y * Q + q) * pitch + x, so one lattice row of every population is one
-// contiguous block of memory.
+// Populations are stored in row bricks (pop_index): population q of a site is
+// q * 64 elements after population 0 of the same site.
 // rows[j] is the (wave-uniform) address of lattice row y + j - 1, cols[i] the
-// per-lane byte offset of column x + i - 1, plane_bytes = pitch * sizeof(raw).
+// per-lane byte offset (col_bytes) of column x + i - 1.
 // The population of direction c arriving at x comes from x - cfl * v: for
 // c_x > 0 it lies between x - 1 (weight a) and x (weight 1 - a), a = cfl |v_x|;
 // for c_x, c_y both non-zero (|v_x| = |v_y|) the bilinear weights are
@@ -132,11 +131,12 @@ struct InterpW {
 };
 
 template <class S, class St, int SM, class T>
-__device__ __forceinline__ void stream_pull(const char* const (&rows)[3], long long plane_bytes,
+__device__ __forceinline__ void stream_pull(const char* const (&rows)[3],
                                             const uint32_t (&cols)[3], const InterpW<T>& W,
                                             T (&f)[St::Q]) {
     constexpr bool UNIT = SM == kStreamUnit;
     using raw = typename S::raw;
+    constexpr long long plane_bytes = kTileW * sizeof(raw);
     sfor<0, St::Q>([&](auto iq) {
         constexpr int q = decltype(iq)::value;
         constexpr Dir d = St::dir[q];
@@ -186,10 +186,11 @@ struct InterpW2 {
 };
 
 template <class S, class St, class T>
-__device__ __forceinline__ void stream_pull_h2(const char* const (&rows)[5], long long plane_bytes,
+__device__ __forceinline__ void stream_pull_h2(const char* const (&rows)[5],
                                                const uint32_t (&cols)[5], const InterpW2<T>& W,
                                                T (&f)[St::Q]) {
     using raw = typename S::raw;
+    constexpr long long plane_bytes = kTileW * sizeof(raw);
     sfor<0, St::Q>([&](auto iq) {
         constexpr int q = decltype(iq)::value;
         constexpr Dir d = St::dir[q];
@@ -351,7 +352,6 @@ struct SiteCtx {
     T ginv, dt;
     int K;                 // largest |kx| of the force table; -1 unforced
     const T* gtab;         // force table of this step
-    long long plane_bytes;
     int eta_s;             // 1: relaxation time tau(eps) = tau eps^(-1/4) (constant eta/s)
 };
 
@@ -364,7 +364,7 @@ __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T
     const T ginv = ctx.ginv, dt = ctx.dt;
     const int K = ctx.K;
     const T* gtab = ctx.gtab;
-    const long long plane_bytes = ctx.plane_bytes;
+    constexpr long long plane_bytes = kTileW * sizeof(raw);
     // (c) moments, Landau frame in FP64
     const Moments<T> m = moments<St, FORCED>(f);
     const double E64 = (double)m.E + (double)S::shift;
