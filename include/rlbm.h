@@ -240,21 +240,30 @@ int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes);
 int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
 
 /* Kernel form and launch shape.  Results never depend on them (bitwise).
- *   RLBM_KERNEL_TILE  -- every thread streams one site from global memory;
- *                        param = tile height th in {1, 2, 4, 8} rows of 64 sites.
- *   RLBM_KERNEL_MARCH -- each wavefront marches down a 64-column strip, loading
- *                        every population row once into a rolling register
- *                        window; param = rows per strip segment (0: chosen
- *                        from the lattice size and the GPU's resident waves).
- * By default the library picks RLBM_KERNEL_MARCH (param 0) for FP32 storage
- * when every resident wavefront gets a segment of at least 8 rows, and
+ *   RLBM_KERNEL_TILE   -- every thread streams one site from global memory;
+ *                         param = tile height th in {1, 2, 4, 8} rows of 64 sites.
+ *   RLBM_KERNEL_MARCH  -- each wavefront marches down a 64-column strip, loading
+ *                         every population row once into a rolling register
+ *                         window; param = rows per strip segment (0: chosen
+ *                         from the lattice size and the GPU's resident waves).
+ *   RLBM_KERNEL_MARCH2 -- two time steps per launch: each wavefront marches
+ *                         down a 62-column strip computing the first step
+ *                         into registers and the second from them, so every
+ *                         population is read and written once per two steps;
+ *                         param as for RLBM_KERNEL_MARCH.  An odd step count
+ *                         ends with one launch of the one-step form.
+ * By default the library advances pairs of steps with RLBM_KERNEL_MARCH2 when
+ * the storage is not FP64 and every resident wavefront gets a segment of at
+ * least 16 rows; one-step launches use RLBM_KERNEL_MARCH (param 0) for FP32
+ * storage when every resident wavefront gets a segment of at least 8 rows,
  * RLBM_KERNEL_TILE with th = 4 otherwise.  With cfl > 1 only the tile form
- * exists (RLBM_KERNEL_MARCH gives EUNSUPPORTED).  rlbm_set_tile(th) is
- * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_autotune times the tile
- * heights and two segment lengths for `steps` steps each (advancing the
- * state) and keeps the fastest; *h_th receives th, or minus the segment
- * length for the marching form.                                            */
-enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1 };
+ * exists (the marching forms give EUNSUPPORTED).  rlbm_set_tile(th) is
+ * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_get_kernel reports the form
+ * that advances the bulk of the steps.  rlbm_autotune times the tile
+ * heights and two segment lengths of each marching form for `steps` steps
+ * each (advancing the state) and keeps the fastest; *h_th receives th, or
+ * minus the segment length for a marching form.                            */
+enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1, RLBM_KERNEL_MARCH2 = 2 };
 int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param);
 int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param);
 int rlbm_set_tile(rlbm_ctx* ctx, int32_t th);
@@ -264,11 +273,11 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th);
  * (0 = direct launches).  Results are identical either way.               */
 int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk);
 
-/* Advance n >= 1 steps exactly like rlbm_step, launching directly, with a
- * HIP event recorded on the context's stream just before and just after
- * every launch of the fused step kernel; synchronises and writes the mean
- * step-kernel duration in milliseconds to *h_ms (the force-table kernel of
- * each step is outside the bracket).  For roofline measurement.           */
+/* n >= 1 launches of the form rlbm_get_kernel reports (n steps, or 2 n for
+ * RLBM_KERNEL_MARCH2), directly, with a HIP event recorded on the context's
+ * stream just before and just after every launch; synchronises and writes
+ * the mean duration of one launch in milliseconds to *h_ms.  For roofline
+ * measurement.                                                             */
 int rlbm_profile_step_kernel(rlbm_ctx* ctx, int64_t n, double* h_ms);
 
 void rlbm_destroy(rlbm_ctx* ctx);
@@ -295,6 +304,8 @@ int rlbm_batch_get_populations(rlbm_batch* b, int32_t r, double* d_out);
 int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk);
 /* rlbm_set_relaxation for every lattice of the ensemble.                   */
 int rlbm_batch_set_relaxation(rlbm_batch* b, int32_t mode);
+/* rlbm_set_kernel for the ensemble's launches.                             */
+int rlbm_batch_set_kernel(rlbm_batch* b, int32_t kind, int32_t param);
 void rlbm_batch_destroy(rlbm_batch* b);
 
 #ifdef __cplusplus

@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
 STENCILS = {"SPH26": 0, "CIRC8": 1, "SPH26_ZFOLD": 2}
 STORAGES = {"F64": 0, "F32": 1, "F16S": 2, "BF16S": 3}
-KERNELS = {"tile": 0, "march": 1}
+KERNELS = {"tile": 0, "march": 1, "march2": 2}
+_KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 RELAXATION = {"constant": 0, "eta_s": 1}
 
 OK, EINVAL, ENOSPACE, EHIP, EUNSTABLE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
@@ -103,6 +104,7 @@ SIGNATURES = [
     ("rlbm_batch_get_populations", _I, [_P, _I32, _P]),
     ("rlbm_batch_set_graph_chunk", _I, [_P, _I32]),
     ("rlbm_batch_set_relaxation", _I, [_P, _I32]),
+    ("rlbm_batch_set_kernel", _I, [_P, _I32, _I32]),
     ("rlbm_batch_destroy", None, [_P]),
 ]
 
@@ -304,7 +306,7 @@ class Lattice:
     def kernel(self):
         k, p = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().rlbm_get_kernel(self._ctx, ctypes.byref(k), ctypes.byref(p)))
-        return ("tile" if k.value == KERNELS["tile"] else "march"), p.value
+        return _KERNEL_NAMES[k.value], p.value
 
     def autotune(self, steps=20):
         th = ctypes.c_int32()
@@ -319,8 +321,9 @@ class Lattice:
         _check(lib().rlbm_set_relaxation(self._ctx, RELAXATION[mode]))
 
     def profile_step_kernel(self, n):
-        """Advance n steps; mean duration (ms) of the fused step kernel, from
-        HIP events recorded around each launch on the library's stream."""
+        """n launches of the current kernel form (2 n steps for "march2");
+        mean duration (ms) of one launch, from HIP events recorded around each
+        launch on the library's stream."""
         ms = ctypes.c_double()
         _check(lib().rlbm_profile_step_kernel(self._ctx, int(n), ctypes.byref(ms)))
         return ms.value
@@ -394,6 +397,9 @@ class Ensemble:
 
     def set_relaxation(self, mode):
         _check(lib().rlbm_batch_set_relaxation(self._b, RELAXATION[mode]))
+
+    def set_kernel(self, kind, param=0):
+        _check(lib().rlbm_batch_set_kernel(self._b, KERNELS[kind], int(param)))
 
     def close(self):
         if self._b:

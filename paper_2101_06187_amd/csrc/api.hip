@@ -95,8 +95,8 @@ int pitch_of(int nx) { return (nx + kTileW - 1) / kTileW * kTileW; }
 // partials, tile map, then per lattice: two population buffers, twiddles,
 // force tables, mode tables).
 struct Layout {
-    size_t ctl = 0, desc = 0, red = 0, tiles = 0, gitems = 0, total = 0;
-    struct Per { size_t buf0, buf1, twx, twy, g0, g1, modes, kptr; };
+    size_t ctl = 0, desc = 0, red = 0, tiles[2] = {0, 0}, gitems[2] = {0, 0}, total = 0;
+    struct Per { size_t buf0, buf1, twx, twy, g[4], modes, kptr; };
     std::vector<Per> per;
     int max_partials = 0;
 };
@@ -112,15 +112,18 @@ int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storag
     long long tiles1 = 0, gitems1 = 0;
     for (int r = 0; r < n_real; ++r) {
         maxp = std::max(maxp, conserved_partials(lats[r].nx, lats[r].ny));
-        tiles1 += (long long)((lats[r].nx + kTileW - 1) / kTileW) * lats[r].ny;
+        // the narrowest work item: one row of a 62-column strip
+        tiles1 += (long long)((lats[r].nx + kTileW - 3) / (kTileW - 2)) * lats[r].ny;
         gitems1 += (long long)(mts[r].K + 1) * ((lats[r].ny + kTileW - 1) / kTileW);
     }
     L.max_partials = maxp;
     L.red = off; off = align_up(off + sizeof(double) * (3 * (size_t)maxp + 8));
-    L.tiles = off;
-    if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)tiles1);
-    L.gitems = off;
-    if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)gitems1);
+    for (int m = 0; m < 2; ++m) {
+        L.tiles[m] = off;
+        if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)tiles1);
+        L.gitems[m] = off;
+        if (n_real > 1) off = align_up(off + sizeof(uint16_t) * (size_t)gitems1);
+    }
     L.per.resize(n_real);
     for (int r = 0; r < n_real; ++r) {
         const size_t plane = (size_t)pitch_of(lats[r].nx) * lats[r].ny;
@@ -130,8 +133,7 @@ int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storag
         P.twx = off; off = align_up(off + cs * 2 * lats[r].nx);
         P.twy = off; off = align_up(off + cs * 2 * lats[r].ny);
         const size_t g = (size_t)lats[r].ny * (mts[r].K + 1) * 4;
-        P.g0 = off; off = align_up(off + cs * g);
-        P.g1 = off; off = align_up(off + cs * g);
+        for (int k = 0; k < 4; ++k) { P.g[k] = off; off = align_up(off + cs * g); }
         P.modes = off; off = align_up(off + sizeof(int4) * mts[r].modes.size());
         P.kptr = off; off = align_up(off + sizeof(int) * mts[r].kptr.size());
     }
@@ -145,6 +147,16 @@ int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storag
 // engine: one or more independent lattices advanced by one launch per step
 // ---------------------------------------------------------------------------
 struct Engine {
+    // One launch configuration: kernel form and work decomposition.
+    struct Cfg {
+        int kind = kKernelTile;
+        int th = 4;                 // wavefronts per block
+        int seglen_req = 0, seglen = 0;
+        int n_tiles = 0, n_gitems = 0, tile_blocks = 0, extra_blocks = 0, grid = 0;
+        uint16_t* d_tiles = nullptr;     // tile -> lattice (ensembles)
+        uint16_t* d_gitems = nullptr;    // force item -> lattice (ensembles)
+    };
+
     int n_real = 0, stencil = 0, storage = 0, Q = 0;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
@@ -155,18 +167,17 @@ struct Engine {
     std::vector<ModeTable> mts;
     std::vector<RealDesc> hdesc;
     RealDesc* d_desc = nullptr;
-    int64_t* d_step = nullptr;
+    int64_t* d_step = nullptr;       // [0] steps, [1] buffer flips
     int* d_flag = nullptr;
     double* d_red = nullptr;
-    uint16_t* d_tiles = nullptr;
-    uint16_t* d_gitems = nullptr;
-    int n_gitems = 0;
-    int smode = kStreamUnit;       // stream mode of the step kernel (all lattices)
+    int smode = kStreamUnit;         // stream mode of the step kernels (all lattices)
     bool any_forced = false;
-    int th = 4, n_tiles = 0, grid = 0, cus = 0, tile_blocks = 0, extra_blocks = 0;
-    int kind = kKernelTile, seglen_req = 0, seglen = 0;
-    bool kind_auto = true;         // until rlbm_set_kernel / rlbm_set_tile / autotune
+    int cus = 0;
+    Cfg cfg[2];                      // [0] one step per launch, [1] two steps per launch
+    bool pairs = false;              // advance pairs of steps with cfg[1]
+    bool kind_auto = true;           // until rlbm_set_kernel / rlbm_set_tile / autotune
     int64_t step = 0;
+    int64_t flips = 0;               // launches since init; the state is in buf[flips & 1]
     int graph_chunk = 0;
     int graph_built_chunk = 0;
     hipGraphExec_t gexec = nullptr;
@@ -183,7 +194,7 @@ struct Engine {
         graph_built_chunk = 0;
     }
 
-    int occupancy() const {
+    int occupancy(int kind, int th) const {
         switch (storage) {
             case RLBM_F64: return occ_f64(kind, stencil, smode, any_forced, th);
             case RLBM_F32: return occ_f32(kind, stencil, smode, any_forced, th);
@@ -192,91 +203,182 @@ struct Engine {
         }
     }
 
-    // work items (tiles of 64 x th sites, or strip segments of 64 columns x
-    // seglen rows for the marching kernel), their maps, the persistent grid
-    // Default form (measured on MI355X): the row-marching kernel when every
-    // wavefront gets a strip segment of at least 8 rows with FP32 storage; the
-    // tile kernel otherwise (small lattices, FP64, 16-bit storage).
+    long long wave_rows(int width) const {
+        long long w = 0;
+        for (int r = 0; r < n_real; ++r)
+            w += (long long)((hdesc[r].nx + width - 1) / width) * hdesc[r].ny;
+        return w;
+    }
+
+    // Default forms (measured on MI355X): one-step launches use the
+    // row-marching kernel when every wavefront gets a strip segment of at
+    // least 8 rows with FP32 storage, the tile kernel otherwise (small
+    // lattices, FP64, 16-bit storage); pairs of steps use the two-step
+    // marching kernel when every wavefront gets a segment of at least
+    // kPairMinRows rows (storage other than FP64, cfl <= 1).
+    static constexpr int kPairMinRows = 16;
     void choose_kind() {
         if (!kind_auto) return;
-        long long wave_rows = 0;
-        for (int r = 0; r < n_real; ++r)
-            wave_rows += (long long)((hdesc[r].nx + kTileW - 1) / kTileW) * hdesc[r].ny;
-        kind = kKernelMarch;
-        th = 4;
-        const long long waves = (long long)cus * occupancy() * 4;
-        const bool long_segments = wave_rows >= 8 * std::max(1LL, waves);
-        kind = (storage == RLBM_F32 && long_segments && smode != kStreamHalo2) ? kKernelMarch
+        Cfg& c = cfg[0];
+        c.th = 4;
+        const long long waves = (long long)cus * occupancy(kKernelMarch, 4) * 4;
+        const bool long_segments = wave_rows(kTileW) >= 8 * std::max(1LL, waves);
+        c.kind = (storage == RLBM_F32 && long_segments && smode != kStreamHalo2) ? kKernelMarch
                                                                                 : kKernelTile;
+        c.seglen_req = 0;
+        const long long waves2 = (long long)cus * occupancy(kKernelMarch2, 4) * 4;
+        pairs = storage != RLBM_F64 && smode != kStreamHalo2 &&
+                wave_rows(kTileW - 2) >= kPairMinRows * std::max(1LL, waves2);
+        cfg[1].kind = kKernelMarch2;
+        cfg[1].th = 4;
+        cfg[1].seglen_req = 0;
+    }
+
+    // work items (tiles of 64 x th sites, or strip segments of 64 (62 for the
+    // two-step kernel) columns x seglen rows), their maps, the persistent grid
+    int configure_map(int m) {
+        Cfg& c = cfg[m];
+        if (c.kind != kKernelTile) c.th = 4;          // 4 wavefronts per block
+        const int per_cu = occupancy(c.kind, c.th);
+        const int slots = cus * per_cu;
+        const int width = c.kind == kKernelMarch2 ? kTileW - 2 : kTileW;
+        int seg = c.seglen_req;
+        if (c.kind != kKernelTile && seg <= 0) {
+            // about one strip segment per resident wavefront, at least 2 rows
+            const long long target = std::max(1LL, (long long)slots * 4);
+            seg = (int)std::max(2LL, (wave_rows(width) + target - 1) / target);
+        }
+        c.seglen = c.kind == kKernelTile ? c.th : seg;
+        c.n_tiles = 0;
+        c.n_gitems = 0;
+        std::vector<uint16_t> map, gmap;
+        const int rows = kTileW * c.th;               // rows per force-table item
+        for (int r = 0; r < n_real; ++r) {
+            RealDesc& d = hdesc[r];
+            WorkMap& w = d.wm[m];
+            w.tiles_x = (d.nx + width - 1) / width;
+            w.seglen = c.seglen;
+            w.tiles_y = (d.ny + w.seglen - 1) / w.seglen;
+            w.tile_begin = c.n_tiles;
+            c.n_tiles += w.tiles_x * w.tiles_y;
+            if (n_real > 1) map.insert(map.end(), (size_t)w.tiles_x * w.tiles_y, (uint16_t)r);
+            w.gitem_begin = c.n_gitems;
+            const int items = d.K >= 0 ? (d.K + 1) * ((d.ny + rows - 1) / rows) : 0;
+            c.n_gitems += items;
+            if (n_real > 1) gmap.insert(gmap.end(), (size_t)items, (uint16_t)r);
+        }
+        if (n_real > 1)
+            HIPCHK(hipMemcpyAsync(c.d_tiles, map.data(), sizeof(uint16_t) * map.size(),
+                                  hipMemcpyHostToDevice, stream));
+        if (n_real > 1 && !gmap.empty())
+            HIPCHK(hipMemcpyAsync(c.d_gitems, gmap.data(), sizeof(uint16_t) * gmap.size(),
+                                  hipMemcpyHostToDevice, stream));
+        const int groups = c.kind == kKernelTile ? c.n_tiles : (c.n_tiles + 3) / 4;
+        c.tile_blocks = std::max(8, std::min(groups, slots));
+        // when the tiles leave resident slots free, build the next force tables
+        // on extra blocks that run alongside the tiles
+        c.extra_blocks = 0;
+        if (any_forced && c.tile_blocks < slots)
+            c.extra_blocks = std::min(2 * c.n_gitems, slots - c.tile_blocks);
+        c.grid = c.tile_blocks + c.extra_blocks;
+        return RLBM_OK;
     }
 
     int configure_tiles() {
         choose_kind();
-        if (kind == kKernelMarch) th = 4;             // 4 wavefronts per block
-        const int per_cu = occupancy();
-        const int slots = cus * per_cu;
-        int seg = seglen_req;
-        if (kind == kKernelMarch && seg <= 0) {
-            // about one strip segment per resident wavefront, at least 2 rows
-            long long wave_rows = 0;
-            for (int r = 0; r < n_real; ++r)
-                wave_rows += (long long)((hdesc[r].nx + kTileW - 1) / kTileW) * hdesc[r].ny;
-            const long long target = std::max(1LL, (long long)slots * 4);
-            seg = (int)std::max(2LL, (wave_rows + target - 1) / target);
-        }
-        seglen = seg;
-        n_tiles = 0;
-        n_gitems = 0;
-        std::vector<uint16_t> map, gmap;
-        const int rows = kTileW * th;                 // rows per force-table item
-        for (int r = 0; r < n_real; ++r) {
-            RealDesc& d = hdesc[r];
-            d.tiles_x = (d.nx + kTileW - 1) / kTileW;
-            d.seglen = kind == kKernelMarch ? seg : th;
-            d.tiles_y = (d.ny + d.seglen - 1) / d.seglen;
-            d.tile_begin = n_tiles;
-            n_tiles += d.tiles_x * d.tiles_y;
-            if (n_real > 1) map.insert(map.end(), (size_t)d.tiles_x * d.tiles_y, (uint16_t)r);
-            d.gitem_begin = n_gitems;
-            const int items = d.K >= 0 ? (d.K + 1) * ((d.ny + rows - 1) / rows) : 0;
-            n_gitems += items;
-            if (n_real > 1) gmap.insert(gmap.end(), (size_t)items, (uint16_t)r);
-        }
+        if (int rc = configure_map(0)) return rc;
+        if (pairs)
+            if (int rc = configure_map(1)) return rc;
         HIPCHK(hipMemcpyAsync(d_desc, hdesc.data(), sizeof(RealDesc) * n_real,
                               hipMemcpyHostToDevice, stream));
-        if (n_real > 1)
-            HIPCHK(hipMemcpyAsync(d_tiles, map.data(), sizeof(uint16_t) * map.size(),
-                                  hipMemcpyHostToDevice, stream));
-        if (n_real > 1 && !gmap.empty())
-            HIPCHK(hipMemcpyAsync(d_gitems, gmap.data(), sizeof(uint16_t) * gmap.size(),
-                                  hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        const int groups = kind == kKernelMarch ? (n_tiles + 3) / 4 : n_tiles;
-        tile_blocks = std::max(8, std::min(groups, slots));
-        // when the tiles leave resident slots free, build the next force table
-        // on extra blocks that run alongside the tiles
-        extra_blocks = 0;
-        if (any_forced && tile_blocks < slots) extra_blocks = std::min(n_gitems, slots - tile_blocks);
-        grid = tile_blocks + extra_blocks;
         drop_graph();
         return RLBM_OK;
     }
 
-    // n steps with events around every step-kernel launch; mean duration in ms
+    // the main form: what rlbm_get_kernel reports and profile times
+    int main_map() const { return pairs ? 1 : 0; }
+
+    StepLaunch make_launch(int m, int step_off, int launch_off, hipStream_t s) const {
+        const Cfg& c = cfg[m];
+        StepLaunch L;
+        L.kind = c.kind;
+        L.args.desc = d_desc;
+        L.args.tile_real = n_real > 1 ? c.d_tiles : nullptr;
+        L.args.gitem_real = n_real > 1 ? c.d_gitems : nullptr;
+        L.args.d_step = d_step;
+        L.args.d_flag = d_flag;
+        L.args.step_off = step_off;
+        L.args.launch_off = launch_off;
+        L.args.nsteps = c.kind == kKernelMarch2 ? 2 : 1;
+        L.args.map = m;
+        L.args.n_tiles = c.n_tiles;
+        L.args.n_gitems = any_forced ? c.n_gitems : 0;
+        L.args.th = c.th;
+        L.args.tile_blocks = c.tile_blocks;
+        L.stencil = stencil;
+        L.smode = smode;
+        L.forced = any_forced;
+        L.grid = c.grid;
+        L.stream = s;
+        return L;
+    }
+
+    hipError_t launch_step_kernel(StepLaunch& L) {
+        switch (storage) {
+            case RLBM_F64: return launch_step_f64(L);
+            case RLBM_F32: return launch_step_f32(L);
+            case RLBM_F16S: return launch_step_f16s(L);
+            default: return launch_step_bf16s(L);
+        }
+    }
+
+    hipError_t launch_on(StepLaunch& L, hipEvent_t before = nullptr, hipEvent_t after = nullptr) {
+        L.ev_start = before;
+        L.ev_stop = after;
+        return launch_step_kernel(L);
+    }
+
+    // Launches for n steps on stream s (pairs first, then a single step);
+    // returns the number of launches through *n_launches.
+    hipError_t issue(int64_t n, hipStream_t s, int64_t* n_launches) {
+        int64_t so = 0, lo = 0;
+        if (pairs)
+            for (; n - so >= 2; so += 2, ++lo) {
+                StepLaunch L = make_launch(1, (int)so, (int)lo, s);
+                if (hipError_t e = launch_on(L)) return e;
+            }
+        for (; so < n; ++so, ++lo) {
+            StepLaunch L = make_launch(0, (int)so, (int)lo, s);
+            if (hipError_t e = launch_on(L)) return e;
+        }
+        *n_launches = lo;
+        return hipSuccess;
+    }
+
+    static int64_t launches_for(int64_t n, bool pairs_on) { return pairs_on ? n / 2 + n % 2 : n; }
+
+    // n launches of the main form with events around every launch; mean
+    // duration per launch in ms (a two-step launch advances two steps)
     int profile(int64_t n, double* avg_ms) {
         if (n < 1 || n > 100000) return fail(RLBM_EINVAL, "n must be in [1, 100000]");
+        const int m = main_map();
+        const int per = m == 1 ? 2 : 1;
         std::vector<hipEvent_t> ev(2 * n, nullptr);
         int rc = RLBM_OK;
         for (auto& e : ev)
             if (hipEventCreate(&e) != hipSuccess) { rc = fail(RLBM_EHIP, "hipEventCreate failed"); break; }
         for (int64_t i = 0; i < n && rc == RLBM_OK; ++i) {
-            StepLaunch L = make_launch((int)i, stream);
+            StepLaunch L = make_launch(m, (int)(i * per), (int)i, stream);
             if (launch_on(L, ev[2 * i], ev[2 * i + 1]) != hipSuccess)
                 rc = fail(RLBM_EHIP, "launch failed while profiling");
         }
-        if (rc == RLBM_OK && launch_advance(d_step, n, stream) != hipSuccess)
+        if (rc == RLBM_OK && launch_advance(d_step, n * per, n, stream) != hipSuccess)
             rc = fail(RLBM_EHIP, "launch failed while profiling");
-        if (rc == RLBM_OK) step += n;
+        if (rc == RLBM_OK) {
+            step += n * per;
+            flips += n;
+        }
         double total = 0;
         if (rc == RLBM_OK && hipEventSynchronize(ev[2 * n - 1]) != hipSuccess)
             rc = fail(RLBM_EHIP, "hipEventSynchronize failed");
@@ -292,66 +394,22 @@ struct Engine {
         return rc;
     }
 
-    StepLaunch make_launch(int step_off, hipStream_t s) const {
-        StepLaunch L;
-        L.kind = kind;
-        L.args.desc = d_desc;
-        L.args.tile_real = n_real > 1 ? d_tiles : nullptr;
-        L.args.gitem_real = n_real > 1 ? d_gitems : nullptr;
-        L.args.d_step = d_step;
-        L.args.d_flag = d_flag;
-        L.args.step_off = step_off;
-        L.args.n_tiles = n_tiles;
-        L.args.n_gitems = any_forced ? n_gitems : 0;
-        L.args.th = th;
-        L.args.tile_blocks = tile_blocks;
-        L.stencil = stencil;
-        L.smode = smode;
-        L.forced = any_forced;
-        L.grid = grid;
-        L.stream = s;
-        return L;
-    }
-
-    hipError_t launch_one(int step_off) {
-        StepLaunch L = make_launch(step_off, stream);
-        return launch_on(L);
-    }
-
-    // one launch per step: the step kernel also builds the next step's force table
-    hipError_t launch_on(StepLaunch& L, hipEvent_t before = nullptr, hipEvent_t after = nullptr) {
-        L.ev_start = before;
-        L.ev_stop = after;
-        return launch_step_kernel(L);
-    }
-
-    // force table of the current step (after the populations were set or loaded)
+    // force tables of the current step and the next (after the populations
+    // were set or loaded)
     int prime_force_table() {
         if (!any_forced) return RLBM_OK;
-        StepLaunch L = make_launch(0, stream);
+        StepLaunch L = make_launch(0, 0, 0, stream);
         HIPCHK(launch_force_table(L.args, storage != RLBM_F64, stream));
         return RLBM_OK;
-    }
-
-    hipError_t launch_step_kernel(StepLaunch& L) {
-        switch (storage) {
-            case RLBM_F64: return launch_step_f64(L);
-            case RLBM_F32: return launch_step_f32(L);
-            case RLBM_F16S: return launch_step_f16s(L);
-            default: return launch_step_bf16s(L);
-        }
     }
 
     int build_graph(int chunk) {
         drop_graph();
         if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t err = hipSuccess;
-        for (int i = 0; i < chunk && err == hipSuccess; ++i) {
-            StepLaunch L = make_launch(i, cap_stream);
-            err = launch_on(L);
-        }
-        if (err == hipSuccess) err = launch_advance(d_step, chunk, cap_stream);
+        int64_t nl = 0;
+        hipError_t err = issue(chunk, cap_stream, &nl);
+        if (err == hipSuccess) err = launch_advance(d_step, chunk, nl, cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
         if (err != hipSuccess || e2 != hipSuccess) {
@@ -373,19 +431,25 @@ struct Engine {
                 int rc = build_graph(graph_chunk);
                 if (rc != RLBM_OK) return rc;
             }
+            const int64_t per_chunk = launches_for(graph_chunk, pairs);
             while (n - done >= graph_chunk) {
                 HIPCHK(hipGraphLaunch(gexec, stream));
                 done += graph_chunk;
+                flips += per_chunk;
             }
         }
         const int64_t rest = n - done;
-        for (int64_t i = 0; i < rest; ++i) HIPCHK(launch_one((int)i));
-        if (rest > 0) HIPCHK(launch_advance(d_step, rest, stream));
+        if (rest > 0) {
+            int64_t nl = 0;
+            HIPCHK(issue(rest, stream, &nl));
+            HIPCHK(launch_advance(d_step, rest, nl, stream));
+            flips += nl;
+        }
         step += n;
         return RLBM_OK;
     }
 
-    int parity() const { return (int)(step & 1); }
+    int parity() const { return (int)(flips & 1); }
 };
 
 struct rlbm_ctx { Engine e; };
@@ -450,11 +514,13 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
     HIPCHK(hipDeviceGetAttribute(&E.cus, hipDeviceAttributeMultiprocessorCount, dev));
 
     E.d_step = (int64_t*)(E.ws + E.lay.ctl);
-    E.d_flag = (int*)(E.ws + E.lay.ctl + 8);
+    E.d_flag = (int*)(E.ws + E.lay.ctl + 16);
     E.d_desc = (RealDesc*)(E.ws + E.lay.desc);
     E.d_red = (double*)(E.ws + E.lay.red);
-    E.d_tiles = (uint16_t*)(E.ws + E.lay.tiles);
-    E.d_gitems = (uint16_t*)(E.ws + E.lay.gitems);
+    for (int m = 0; m < 2; ++m) {
+        E.cfg[m].d_tiles = (uint16_t*)(E.ws + E.lay.tiles[m]);
+        E.cfg[m].d_gitems = (uint16_t*)(E.ws + E.lay.gitems[m]);
+    }
     E.hdesc.assign(n_real, RealDesc{});
     E.smode = kStreamUnit;
     E.any_forced = false;
@@ -468,8 +534,7 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         d.buf[1] = E.ws + P.buf1;
         d.twx = E.ws + P.twx;
         d.twy = E.ws + P.twy;
-        d.g[0] = E.ws + P.g0;
-        d.g[1] = E.ws + P.g1;
+        for (int k = 0; k < 4; ++k) d.g[k] = E.ws + P.g[k];
         d.modes = (const int4*)(E.ws + P.modes);
         d.kptr = (const int*)(E.ws + P.kptr);
         d.nx = lat.nx;
@@ -531,7 +596,7 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         }
         HIPCHK(hipStreamSynchronize(E.stream));
     }
-    HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
+    HIPCHK(launch_reset(E.d_step, 0, E.flips, E.d_flag, E.stream));
     E.step = 0;
     return E.configure_tiles();
 }
@@ -552,7 +617,7 @@ int engine_set_state(Engine& E, int r, const double* d_e, const double* d_ux,
                      const double* d_uy, bool reset_step) {
     if (!d_e || !d_ux || !d_uy) return fail(RLBM_EINVAL, "NULL field pointer");
     if (reset_step) {
-        HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
+        HIPCHK(launch_reset(E.d_step, 0, E.flips, E.d_flag, E.stream));
         E.step = 0;
     }
     HIPCHK(launch_set_state(E.d_desc, r, E.storage, E.stencil, E.lats[r].nx, E.lats[r].ny, d_e,
@@ -742,7 +807,7 @@ int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in) {
     if (int rc = check_ctx(ctx)) return rc;
     if (!d_in) return fail(RLBM_EINVAL, "NULL input");
     Engine& E = ctx->e;
-    HIPCHK(launch_reset(E.d_step, 0, E.d_flag, E.stream));
+    HIPCHK(launch_reset(E.d_step, 0, E.flips, E.d_flag, E.stream));
     E.step = 0;
     HIPCHK(launch_set_populations(E.d_desc, 0, E.storage, E.stencil, E.lats[0].nx, E.lats[0].ny, d_in,
                                   E.parity(), E.stream));
@@ -932,7 +997,7 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
         h.tau_mode != E.hdesc[0].tau_mode || h.step < 0)
         return fail(RLBM_EINVAL, "checkpoint of another configuration");
     E.step = h.step;
-    HIPCHK(launch_reset(E.d_step, h.step, E.d_flag, E.stream));
+    HIPCHK(launch_reset(E.d_step, h.step, E.flips, E.d_flag, E.stream));
     const RealDesc& d = E.hdesc[0];
     const char* src = (const char*)h_buf + sizeof(h);
     HIPCHK(hipMemcpyAsync(d.buf[E.parity()], src, need - sizeof(h), hipMemcpyHostToDevice,
@@ -942,41 +1007,54 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes) {
     return RLBM_OK;
 }
 
-int rlbm_set_tile(rlbm_ctx* ctx, int32_t th) {
-    if (int rc = check_ctx(ctx)) return rc;
-    if (th != 1 && th != 2 && th != 4 && th != 8) return fail(RLBM_EINVAL, "tile height must be 1, 2, 4 or 8");
-    ctx->e.kind = kKernelTile;
-    ctx->e.kind_auto = false;
-    ctx->e.th = th;
-    return ctx->e.configure_tiles();
+int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
+    if (kind == RLBM_KERNEL_TILE) {
+        if (param != 1 && param != 2 && param != 4 && param != 8)
+            return fail(RLBM_EINVAL, "tile height must be 1, 2, 4 or 8");
+        E.cfg[0].kind = kKernelTile;
+        E.cfg[0].th = param;
+        E.pairs = false;
+    } else if (kind == RLBM_KERNEL_MARCH || kind == RLBM_KERNEL_MARCH2) {
+        if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
+        if (E.smode == kStreamHalo2)
+            return fail(RLBM_EUNSUPPORTED, "the row-marching forms need cfl <= 1");
+        if (kind == RLBM_KERNEL_MARCH) {
+            E.cfg[0].kind = kKernelMarch;
+            E.cfg[0].seglen_req = param;
+            E.pairs = false;
+        } else {
+            E.cfg[1].kind = kKernelMarch2;
+            E.cfg[1].seglen_req = param;
+            E.pairs = true;
+        }
+    } else {
+        return fail(RLBM_EINVAL, "unknown kernel kind");
+    }
+    E.kind_auto = false;
+    return E.configure_tiles();
 }
 
 int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param) {
     if (int rc = check_ctx(ctx)) return rc;
-    Engine& E = ctx->e;
-    E.kind_auto = false;
-    if (kind == RLBM_KERNEL_TILE) {
-        if (param != 1 && param != 2 && param != 4 && param != 8)
-            return fail(RLBM_EINVAL, "tile height must be 1, 2, 4 or 8");
-        E.kind = kKernelTile;
-        E.th = param;
-    } else if (kind == RLBM_KERNEL_MARCH) {
-        if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
-        if (E.smode == kStreamHalo2)
-            return fail(RLBM_EUNSUPPORTED, "the row-marching form needs cfl <= 1");
-        E.kind = kKernelMarch;
-        E.seglen_req = param;
-    } else {
-        return fail(RLBM_EINVAL, "unknown kernel kind");
-    }
-    return E.configure_tiles();
+    return engine_set_kernel(ctx->e, kind, param);
 }
+
+int rlbm_set_tile(rlbm_ctx* ctx, int32_t th) { return rlbm_set_kernel(ctx, RLBM_KERNEL_TILE, th); }
 
 int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param) {
     if (int rc = check_ctx(ctx)) return rc;
     if (!h_kind || !h_param) return fail(RLBM_EINVAL, "NULL output");
-    *h_kind = ctx->e.kind == kKernelMarch ? RLBM_KERNEL_MARCH : RLBM_KERNEL_TILE;
-    *h_param = ctx->e.kind == kKernelMarch ? ctx->e.seglen : ctx->e.th;
+    const Engine& E = ctx->e;
+    if (E.pairs) {
+        *h_kind = RLBM_KERNEL_MARCH2;
+        *h_param = E.cfg[1].seglen;
+    } else if (E.cfg[0].kind == kKernelMarch) {
+        *h_kind = RLBM_KERNEL_MARCH;
+        *h_param = E.cfg[0].seglen;
+    } else {
+        *h_kind = RLBM_KERNEL_TILE;
+        *h_param = E.cfg[0].th;
+    }
     return RLBM_OK;
 }
 
@@ -987,18 +1065,23 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    E.kind_auto = false;
+    steps += steps & 1;                           // whole pairs for the two-step form
     float best = 1e30f;
-    int best_kind = E.kind, best_param = E.kind == kKernelMarch ? E.seglen_req : E.th;
-    const int cand[6][2] = {{kKernelTile, 1}, {kKernelTile, 2}, {kKernelTile, 4}, {kKernelTile, 8},
-                            {kKernelMarch, 0}, {kKernelMarch, -1}};
+    int best_kind = -1, best_param = 0;
+    // (kind, parameter): tile heights; marching forms with the automatic
+    // segment length (0) and twice it (-1)
+    const int cand[8][2] = {{RLBM_KERNEL_TILE, 1},  {RLBM_KERNEL_TILE, 2},  {RLBM_KERNEL_TILE, 4},
+                            {RLBM_KERNEL_TILE, 8},  {RLBM_KERNEL_MARCH, 0}, {RLBM_KERNEL_MARCH, -1},
+                            {RLBM_KERNEL_MARCH2, 0}, {RLBM_KERNEL_MARCH2, -1}};
+    int auto_seg[3] = {0, 0, 0};
     for (const auto& c : cand) {
-        if (c[0] == kKernelMarch && E.smode == kStreamHalo2) continue;
-        E.kind = c[0];
-        if (c[0] == kKernelTile) E.th = c[1];
-        else E.seglen_req = c[1] == 0 ? 0 : std::max(2, 2 * E.seglen);   // auto, then twice as long
-        if (int rc = E.configure_tiles()) return rc;
-        if (int rc = E.run(1)) return rc;
+        if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
+        const int param = c[1] >= 0 ? c[1] : std::max(2, 2 * auto_seg[c[0]]);
+        if (int rc = rlbm_set_kernel(ctx, c[0], param)) return rc;
+        int32_t k = 0, p = 0;
+        rlbm_get_kernel(ctx, &k, &p);
+        if (c[1] == 0) auto_seg[c[0]] = p;
+        if (int rc = E.run(2)) return rc;
         HIPCHK(hipEventRecord(e0, E.stream));
         if (int rc = E.run(steps)) return rc;
         HIPCHK(hipEventRecord(e1, E.stream));
@@ -1007,17 +1090,14 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best) {
             best = ms;
-            best_kind = E.kind;
-            best_param = E.kind == kKernelMarch ? E.seglen : E.th;
+            best_kind = k;
+            best_param = p;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    E.kind = best_kind;
-    if (best_kind == kKernelTile) E.th = best_param;
-    else E.seglen_req = best_param;
-    if (h_th) *h_th = best_kind == kKernelMarch ? -best_param : best_param;
-    return E.configure_tiles();
+    if (h_th) *h_th = best_kind == RLBM_KERNEL_TILE ? best_param : -best_param;
+    return rlbm_set_kernel(ctx, best_kind, best_param);
 }
 
 int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk) {
@@ -1099,6 +1179,11 @@ int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk) {
     if (chunk < 0 || chunk > 4096) return fail(RLBM_EINVAL, "chunk must be in [0, 4096]");
     b->e.graph_chunk = chunk;
     return RLBM_OK;
+}
+
+int rlbm_batch_set_kernel(rlbm_batch* b, int32_t kind, int32_t param) {
+    if (int rc = check_ctx(b)) return rc;
+    return engine_set_kernel(b->e, kind, param);
 }
 
 int rlbm_batch_set_relaxation(rlbm_batch* b, int32_t mode) {

@@ -14,26 +14,32 @@ namespace rlbm {
 constexpr int kTileW = 64;            // sites per tile row = one wavefront
 constexpr int kMaxTileH = 8;
 
+// Work decomposition of one lattice for one launch configuration.
+struct WorkMap {
+    int tiles_x, tiles_y;
+    int tile_begin;               // first work item (tile or strip segment) of this lattice
+    int seglen;                   // rows per strip segment (marching kernels)
+    int gitem_begin;              // first force-table work item of this lattice
+};
+
 // Per-lattice descriptor, resident in the workspace; every field is read
 // once per tile and made wave-uniform.
 struct RealDesc {
-    void* buf[2];                 // population buffers; step s reads buf[s & 1]
+    void* buf[2];                 // population buffers; the current state is in
+                                  // buf[flips & 1], flips = launches so far
     const void* twx;              // [nx][2] cos, sin of 2 pi x / nx (compute type)
     const void* twy;              // [ny][2] cos, sin of 2 pi y / ny (compute type)
-    void* g[2];                   // force table of step s in g[s & 1]:
+    void* g[4];                   // force table of step s in g[s & 3]:
                                   //   [ny][K+1][4] = Px, Qx, Py, Qy (compute type)
     const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
     const int* kptr;              // K+2 offsets into modes
     int nx, ny;
     int pitch;                    // nx rounded up to 64; see pop_index for the layout
-    int tiles_x, tiles_y;
-    int tile_begin;               // first work item (tile or strip segment) of this lattice
-    int seglen;                   // rows per strip segment (marching kernel)
+    WorkMap wm[2];                // [0]: one-step launches, [1]: two-step launches
     int K;                        // largest |kx| of the driven modes; -1 unforced
     int n_modes;
     int realization;              // Philox counter word 2
     int tau_mode;                 // RLBM_TAU_CONSTANT or RLBM_TAU_ETA_S
-    int gitem_begin;              // first force-table work item of this lattice
     uint64_t seed;
     double amplitude;
     double inv_tau;               // 1 / tau
@@ -47,18 +53,24 @@ struct RealDesc {
 };
 
 // A force-table work item covers one |kx| = k and 64 * th consecutive rows.
+// A launch that advances steps [s, s + nsteps) reads the force tables of
+// those steps and builds the tables of steps s + nsteps and s + nsteps + 1,
+// so any sequence of one- and two-step launches finds its tables ready.
 struct StepArgs {
     const RealDesc* desc;         // device array of descriptors
     const uint16_t* tile_real;    // tile -> lattice, NULL when there is one lattice
     const uint16_t* gitem_real;   // force item -> lattice, NULL when there is one lattice
-    const int64_t* d_step;        // device step counter (base)
+    const int64_t* d_step;        // [0]: step counter, [1]: buffer flips (launches)
     int* d_flag;                  // stability flag
-    int step_off;                 // this launch computes step *d_step + step_off
+    int step_off;                 // this launch starts at step d_step[0] + step_off
+    int launch_off;               // and reads buf[(d_step[1] + launch_off) & 1]
+    int nsteps;                   // steps advanced by this launch (1 or 2)
+    int map;                      // work map (RealDesc::wm) of this launch
     int n_tiles;
-    int n_gitems;                 // force-table items of the next step (0: unforced)
-    int th;                       // tile height (rows of 64 sites)
+    int n_gitems;                 // force-table items of one table (0: unforced)
+    int th;                       // wavefronts per block (tile height of the tile form)
     int tile_blocks;              // blocks [0, tile_blocks) walk the tiles; any further
-                                  // blocks only build the next force table
+                                  // blocks only build force tables
 };
 
 // Population layout in HBM ("row bricks").  Lattice row y is one contiguous
@@ -76,7 +88,7 @@ __host__ __device__ inline uint32_t col_bytes(int x, int Q) {
     return (uint32_t)(((x >> 6) * (Q * kTileW) + (x & 63)) * (int)sizeof(Raw));
 }
 
-enum { kKernelTile = 0, kKernelMarch = 1 };
+enum { kKernelTile = 0, kKernelMarch = 1, kKernelMarch2 = 2 };
 
 // Stream modes: general cfl <= 1; cfl == 1 (axis populations move exactly
 // one node); 1 < cfl <= 2 (sources up to two nodes upstream, tile form only).
@@ -107,8 +119,8 @@ int occ_bf16s(int kind, int stencil, int smode, bool forced, int th);
 
 // Force table of the current step (kernels_aux.hip), for initial states.
 hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s);
-hipError_t launch_advance(int64_t* d_step, int64_t by, hipStream_t s);
-hipError_t launch_reset(int64_t* d_step, int64_t value, int* d_flag, hipStream_t s);
+hipError_t launch_advance(int64_t* d_step, int64_t steps, int64_t flips, hipStream_t s);
+hipError_t launch_reset(int64_t* d_step, int64_t step, int64_t flips, int* d_flag, hipStream_t s);
 hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int stencil,
                             int nx, int ny, const double* e, const double* ux,
                             const double* uy, int parity, hipStream_t s);

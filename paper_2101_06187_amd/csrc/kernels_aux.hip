@@ -12,16 +12,20 @@ namespace rlbm {
 // step after it; this fills the first one after a state is set or loaded)
 // ---------------------------------------------------------------------------
 template <class T>
+// the tables of steps d_step[0] + step_off and the step after it
 __global__ void force_table_kernel(StepArgs A) {
-    const int u = blockIdx.x;
+    const int v = blockIdx.x;
+    const int second = v >= A.n_gitems;
+    const int u = second ? v - A.n_gitems : v;
     const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
     const RealDesc& Dsc = A.desc[r];
-    force_item<T>(Dsc, u - uni(Dsc.gitem_begin), *A.d_step + A.step_off, kTileW * A.th);
+    force_item<T>(Dsc, u - uni(Dsc.wm[A.map].gitem_begin), A.d_step[0] + A.step_off + second,
+                  kTileW * A.th);
 }
 
 hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s) {
     if (a.n_gitems <= 0) return hipSuccess;
-    const dim3 grid(a.n_gitems), block(kTileW, a.th);
+    const dim3 grid(2 * a.n_gitems), block(kTileW, a.th);
     if (fp32) hipLaunchKernelGGL(force_table_kernel<float>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(force_table_kernel<double>, grid, block, 0, s, a);
     return hipGetLastError();
@@ -30,26 +34,28 @@ hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // step counter and stability flag
 // ---------------------------------------------------------------------------
-__global__ void advance_kernel(int64_t* d_step, int64_t by) {
+__global__ void advance_kernel(int64_t* d_step, int64_t steps, int64_t flips) {
     if (threadIdx.x == 0) {
         volatile int64_t* p = d_step;
-        *p = *p + by;
+        p[0] = p[0] + steps;
+        p[1] = p[1] + flips;
     }
 }
-__global__ void reset_kernel(int64_t* d_step, int64_t value, int* d_flag) {
+__global__ void reset_kernel(int64_t* d_step, int64_t step, int64_t flips, int* d_flag) {
     if (threadIdx.x == 0) {
         volatile int64_t* p = d_step;
         volatile int* q = d_flag;
-        *p = value;
+        p[0] = step;
+        p[1] = flips;
         *q = 0;
     }
 }
-hipError_t launch_advance(int64_t* d_step, int64_t by, hipStream_t s) {
-    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, d_step, by);
+hipError_t launch_advance(int64_t* d_step, int64_t steps, int64_t flips, hipStream_t s) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, d_step, steps, flips);
     return hipGetLastError();
 }
-hipError_t launch_reset(int64_t* d_step, int64_t value, int* d_flag, hipStream_t s) {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, d_step, value, d_flag);
+hipError_t launch_reset(int64_t* d_step, int64_t step, int64_t flips, int* d_flag, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, d_step, step, flips, d_flag);
     return hipGetLastError();
 }
 

@@ -32,6 +32,21 @@ using Store = StF16S;
 using Store = StBF16S;
 #endif
 
+// Force tables of the steps after this launch (s + nsteps and the one after
+// it): 2 n_gitems items; this block takes items u0, u0 + du, ...
+template <class T>
+__device__ __forceinline__ void build_force_tables(const StepArgs& A, int64_t step, int u0, int du) {
+    const int n = A.n_gitems;
+    for (int v = u0 >= 0 ? u0 : 2 * n; v < 2 * n; v += du) {
+        const int second = v >= n;
+        const int u = second ? v - n : v;
+        const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
+        const RealDesc& Dsc = A.desc[r];
+        force_item<T>(Dsc, u - uni(Dsc.wm[A.map].gitem_begin), step + A.nsteps + second,
+                      kTileW * A.th);
+    }
+}
+
 template <class S, class St, int SM, bool FORCED>
 __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     using T = typename S::T;
@@ -39,8 +54,8 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     constexpr int D = St::D;
     constexpr bool F64 = std::is_same<T, double>::value;
 
-    const int64_t step = *A.d_step + A.step_off;
-    const int par = (int)(step & 1);
+    const int64_t step = A.d_step[0] + A.step_off;
+    const int par = (int)((A.d_step[1] + A.launch_off) & 1);
     const int lx = threadIdx.x;
     const int ly = threadIdx.y;
 
@@ -74,8 +89,8 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             const RealDesc& Dsc = A.desc[r];
             nx = uni(Dsc.nx);
             ny = uni(Dsc.ny);
-            tiles_x = uni(Dsc.tiles_x);
-            tile_begin = uni(Dsc.tile_begin);
+            tiles_x = uni(Dsc.wm[A.map].tiles_x);
+            tile_begin = uni(Dsc.wm[A.map].tile_begin);
             const int pitch = uni(Dsc.pitch);
             rowq_bytes = (long long)pitch * St::Q * (long long)sizeof(raw);
             src = (const char*)uni(Dsc.buf[par]);
@@ -95,7 +110,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             if constexpr (FORCED) {
                 K = uni(Dsc.K);
                 twp = uni((const T*)Dsc.twx);
-                gtab = uni((const T*)Dsc.g[par]);
+                gtab = uni((const T*)Dsc.g[step & 3]);
             }
             dq = nb / tiles_x;
             dr = nb - dq * tiles_x;
@@ -160,13 +175,8 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     // else the items of each XCD spread over its tile blocks
     if constexpr (FORCED) {
         const int extra = (int)gridDim.x - G;
-        const int u0 = extra > 0 ? b - G : xcd + 8 * (b >> 3);
-        const int du = extra > 0 ? extra : 8 * nb;
-        for (int u = u0 >= 0 ? u0 : A.n_gitems; u < A.n_gitems; u += du) {
-            const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
-            const RealDesc& Dsc = A.desc[r];
-            force_item<T>(Dsc, u - uni(Dsc.gitem_begin), step + 1, kTileW * A.th);
-        }
+        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+                              extra > 0 ? extra : 8 * nb);
     }
 }
 
@@ -269,8 +279,8 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
     constexpr int NH = M::nH();
     constexpr bool F64 = std::is_same<T, double>::value;
 
-    const int64_t step = *A.d_step + A.step_off;
-    const int par = (int)(step & 1);
+    const int64_t step = A.d_step[0] + A.step_off;
+    const int par = (int)((A.d_step[1] + A.launch_off) & 1);
     const int lane = threadIdx.x;
     const int wv = uni((int)threadIdx.y);   // one wavefront per row of the block
 
@@ -290,9 +300,9 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
         const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
-        const int strips = uni(Dsc.tiles_x);
-        const int seglen = uni(Dsc.seglen);
-        const int local = u - uni(Dsc.tile_begin);
+        const int strips = uni(Dsc.wm[A.map].tiles_x);
+        const int seglen = uni(Dsc.wm[A.map].seglen);
+        const int local = u - uni(Dsc.wm[A.map].tile_begin);
         const int seg = local / strips;
         const int strip = local - seg * strips;
         const int ya = seg * seglen;
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
         T c1 = 0, s1 = 0;
         if constexpr (FORCED) {
             sctx.K = uni(Dsc.K);
-            sctx.gtab = uni((const T*)Dsc.g[par]);
+            sctx.gtab = uni((const T*)Dsc.g[step & 3]);
             if (sctx.K >= 0 && active) {
                 const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
                 c1 = twx[2 * x];
@@ -437,13 +447,252 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
 
     if constexpr (FORCED) {
         const int extra = (int)gridDim.x - G;
-        const int u0 = extra > 0 ? b - G : xcd + 8 * (b >> 3);
-        const int du = extra > 0 ? extra : 8 * nb;
-        for (int u = u0 >= 0 ? u0 : A.n_gitems; u < A.n_gitems; u += du) {
-            const int r = A.gitem_real ? uni((int)A.gitem_real[u]) : 0;
-            const RealDesc& Dsc = A.desc[r];
-            force_item<T>(Dsc, u - uni(Dsc.gitem_begin), step + 1, kTileW * A.th);
+        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+                              extra > 0 ? extra : 8 * nb);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch, row-marching.  A wavefront owns a strip of 62 output
+// columns [x0, x0 + 62) and marches down its segment of rows [ya, yb) as in
+// march_kernel, with 64 lanes on the columns x0 - 1 .. x0 + 62:
+//   at step-n row r it streams the input (rolling window, lane exchange, halo
+//   gathers for the columns x0 - 2 and x0 + 63) and applies update_site for
+//   step s, keeping the new populations in registers (rounded to the storage
+//   type, exactly as a one-step launch stores and reloads them);
+//   it then streams step s + 1 at row r - 1 from the step-s rows r - 2, r - 1,
+//   r held in registers (neighbours by lane exchange, no halo needed for
+//   lanes 1..62) and stores rows [ya, yb) of step s + 2.
+// Every population is read and written once per two steps; the step-s rows
+// ya - 1 and yb and the two edge lanes are computed twice (by the
+// neighbouring segment or strip).  The per-site arithmetic is the same
+// update_site as every other form, so results are bitwise identical.
+// ---------------------------------------------------------------------------
+template <class S, class St, int SM, bool FORCED>
+__global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
+    static_assert(SM != kStreamHalo2, "the row-marching form streams from the nearest rows only");
+    constexpr bool UNIT = SM == kStreamUnit;
+    using T = typename S::T;
+    using raw = typename S::raw;
+    using M = MarchMap<St>;
+    constexpr int Q = St::Q;
+    constexpr int NH = M::nH();
+    constexpr bool F64 = std::is_same<T, double>::value;
+    constexpr int kOut = kTileW - 2;          // output columns per strip
+
+    const int64_t step = A.d_step[0] + A.step_off;
+    const int par = (int)((A.d_step[1] + A.launch_off) & 1);
+    const int lane = threadIdx.x;
+    const int wv = uni((int)threadIdx.y);
+
+    const int G = A.tile_blocks;
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int nb = (G - xcd + 7) >> 3;
+    const int n_groups = (A.n_tiles + 3) >> 2;
+    const int chunk = (n_groups + 7) >> 3;
+    const int g_end = min(n_groups, (xcd + 1) * chunk);
+
+    for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
+        const int u = grp * 4 + wv;
+        if (u >= A.n_tiles) continue;
+        const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
+        const RealDesc& Dsc = A.desc[r];
+        const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
+        const int strips = uni(Dsc.wm[A.map].tiles_x);
+        const int seglen = uni(Dsc.wm[A.map].seglen);
+        const int local = u - uni(Dsc.wm[A.map].tile_begin);
+        const int seg = local / strips;
+        const int strip = local - seg * strips;
+        const int ya = seg * seglen;
+        const int yb = min(ny, ya + seglen);
+        const int x0 = strip * kOut;
+        auto wrapx = [&](int v) { v %= nx; return v < 0 ? v + nx : v; };
+        const int xl = wrapx(x0 - 1 + lane);     // column of this lane (both steps)
+        const bool out_lane = lane >= 1 && lane <= kOut && x0 + lane - 1 < nx;
+        constexpr long long plane_bytes = kTileW * sizeof(raw);
+        const long long rowq = (long long)uni(Dsc.pitch) * Q * (long long)sizeof(raw);
+        const char* src = (const char*)uni(Dsc.buf[par]);
+        char* dst = (char*)uni(Dsc.buf[par ^ 1]);
+        InterpW<T> W;
+        SiteCtx<T> c0, c1x;                       // contexts of steps s and s + 1
+        if constexpr (F64) {
+            W.set(uni(Dsc.a[0]), uni(Dsc.a[1]), uni(Dsc.a[2]));
+            c0.ginv = uni(Dsc.inv_tau);
+            c0.dt = uni(Dsc.dt);
+        } else {
+            W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
+            c0.ginv = uni(Dsc.inv_tauf);
+            c0.dt = uni(Dsc.dtf);
         }
+        c0.K = -1;
+        c0.eta_s = uni(Dsc.tau_mode);
+        c0.gtab = nullptr;
+        T cs = 0, sn = 0;
+        if constexpr (FORCED) {
+            c0.K = uni(Dsc.K);
+            c0.gtab = uni((const T*)Dsc.g[step & 3]);
+            if (c0.K >= 0) {
+                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
+                cs = twx[2 * xl];
+                sn = twx[2 * xl + 1];
+            }
+        }
+        c1x = c0;
+        if constexpr (FORCED) c1x.gtab = uni((const T*)Dsc.g[(step + 1) & 3]);
+        const uint32_t colb = col_bytes<raw>(xl, Q);
+        auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
+        auto ld = [&](int q, int yy) -> T {
+            const char* rowp = src + (long long)wrap(yy) * rowq + (long long)q * plane_bytes;
+            return (T)S::ld((gp<const raw>)(rowp + colb));
+        };
+        // halo gather of the input: lane j < NH holds the halo of the j-th
+        // population with c_x != 0 (columns x0 - 2 and x0 + 63)
+        int my_q = 0, my_dy = 0;
+        bool my_left = true;
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            if constexpr (M::cx(q) != 0) {
+                if (lane == M::hidx(q)) {
+                    my_q = q;
+                    my_dy = M::cy(q) < 0 ? 1 : 0;
+                    my_left = M::cx(q) > 0;
+                }
+            }
+        });
+        const int hcol = my_left ? wrapx(x0 - 2) : wrapx(x0 + kTileW - 1);
+        auto gather = [&](int yy) -> T {
+            T h = 0;
+            if (lane < NH) {
+                const char* p = src + (long long)wrap(yy + my_dy) * rowq +
+                                (long long)my_q * plane_bytes + col_bytes<raw>(hcol, Q);
+                h = (T)S::ld((gp<const raw>)p);
+            }
+            return h;
+        };
+
+        // step-s rows r0 .. r1 feed the outputs ya .. yb - 1
+        const int r0 = ya - 1, r1 = yb;
+        T cur[Q], pre[Q], up[M::nU], dn[M::nD];   // input window (as march_kernel)
+        T sc[Q], su[M::nU];                       // step-s rows r - 1 (all), r - 2 (c_y > 0)
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            cur[q] = ld(q, r0);
+            if constexpr (M::cy(q) > 0) up[M::uidx(q)] = ld(q, r0 - 1);
+            if constexpr (M::cy(q) < 0) dn[M::didx(q)] = ld(q, r0 + 1);
+        });
+        T hp = gather(r0 - 1);
+        T hc = gather(r0);
+        T hn = 0;
+
+        for (int rr = r0; rr <= r1; ++rr) {
+            if (rr < r1) {                       // next input row in flight
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    pre[q] = ld(q, M::cy(q) < 0 ? rr + 2 : rr + 1);
+                });
+                hn = gather(rr + 1);
+            }
+            // step s at row rr, every lane
+            T f[Q];
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                constexpr Dir d = St::dir[q];
+                constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+                const T own = cur[q];
+                T vert = own;
+                if constexpr (d.cy > 0) vert = up[M::uidx(q)];
+                if constexpr (d.cy < 0) vert = dn[M::didx(q)];
+                if constexpr (d.cx == 0 && d.cy == 0) {
+                    f[q] = own;
+                } else if constexpr (d.cx == 0) {
+                    if constexpr (UNIT && n == 1) f[q] = vert;
+                    else f[q] = lerp(own, vert, W.a[n - 1]);
+                } else {
+                    constexpr int H = M::hidx(q);
+                    const int addr = (lane - d.cx) * 4;
+                    const int fix = d.cx > 0 ? 0 : kTileW - 1;
+                    const T h_own = read_lane(d.cy < 0 ? hp : hc, H);
+                    const T own_nb = write_lane(lane_from(own, addr), h_own, fix);
+                    if constexpr (d.cy == 0) {
+                        if constexpr (UNIT && n == 1) f[q] = own_nb;
+                        else f[q] = lerp(own, own_nb, W.a[n - 1]);
+                    } else {
+                        const T h_vert = read_lane(d.cy > 0 ? hp : hc, H);
+                        const T vert_nb = write_lane(lane_from(vert, addr), h_vert, fix);
+                        f[q] = fma(W.w11[n - 1], vert_nb,
+                                   fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                    }
+                }
+            });
+            T fn[Q];
+            update_site_to<S, St, FORCED>(
+                f, c0, cs, sn, wrap(rr),
+                [&](auto qc, T v) {
+                    constexpr int q = decltype(qc)::value;
+                    raw t;
+                    S::st(&t, v);                  // the value a one-step launch stores
+                    fn[q] = (T)S::ld(&t);
+                },
+                A.d_flag);
+            // step s + 1 at row rr - 1 from step-s rows rr - 2, rr - 1, rr
+            if (rr >= ya + 1) {
+                T g[Q];
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    constexpr Dir d = St::dir[q];
+                    constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+                    const T own = sc[q];
+                    T vert = own;
+                    if constexpr (d.cy > 0) vert = su[M::uidx(q)];
+                    if constexpr (d.cy < 0) vert = fn[q];
+                    if constexpr (d.cx == 0 && d.cy == 0) {
+                        g[q] = own;
+                    } else if constexpr (d.cx == 0) {
+                        if constexpr (UNIT && n == 1) g[q] = vert;
+                        else g[q] = lerp(own, vert, W.a[n - 1]);
+                    } else {
+                        const int addr = (lane - d.cx) * 4;
+                        const T own_nb = lane_from(own, addr);
+                        if constexpr (d.cy == 0) {
+                            if constexpr (UNIT && n == 1) g[q] = own_nb;
+                            else g[q] = lerp(own, own_nb, W.a[n - 1]);
+                        } else {
+                            const T vert_nb = lane_from(vert, addr);
+                            g[q] = fma(W.w11[n - 1], vert_nb,
+                                       fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                        }
+                    }
+                });
+                if (out_lane)
+                    update_site<S, St, FORCED>(g, c1x, cs, sn, rr - 1,
+                                               (gp<char>)(dst + (long long)(rr - 1) * rowq), colb,
+                                               A.d_flag);
+            }
+            // roll the step-s window and the input window
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                if constexpr (M::cy(q) > 0) su[M::uidx(q)] = sc[q];
+                sc[q] = fn[q];
+                if constexpr (M::cy(q) > 0) {
+                    up[M::uidx(q)] = cur[q];
+                    cur[q] = pre[q];
+                } else if constexpr (M::cy(q) < 0) {
+                    cur[q] = dn[M::didx(q)];
+                    dn[M::didx(q)] = pre[q];
+                } else {
+                    cur[q] = pre[q];
+                }
+            });
+            hp = hc;
+            hc = hn;
+        }
+    }
+
+    if constexpr (FORCED) {
+        const int extra = (int)gridDim.x - G;
+        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+                              extra > 0 ? extra : 8 * nb);
     }
 }
 
@@ -451,9 +700,10 @@ template <class St, int SM, bool FORCED>
 static const void* kernel_ptr(int kind) {
     if constexpr (SM == kStreamHalo2) {
         // cfl > 1: tile form only
-        return kind == kKernelMarch ? nullptr : (const void*)step_kernel<Store, St, SM, FORCED>;
+        return kind == kKernelTile ? (const void*)step_kernel<Store, St, SM, FORCED> : nullptr;
     } else {
         if (kind == kKernelMarch) return (const void*)march_kernel<Store, St, SM, FORCED>;
+        if (kind == kKernelMarch2) return (const void*)march2_kernel<Store, St, SM, FORCED>;
         return (const void*)step_kernel<Store, St, SM, FORCED>;
     }
 }

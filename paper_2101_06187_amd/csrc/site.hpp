@@ -10,6 +10,12 @@
 
 #include "engine.hpp"
 
+// Only the fma() calls written out below fuse a multiply and an add: the
+// compiler does not contract other a * b + c on its own.  Every kernel form
+// inlines the same per-site code into different surroundings, and this keeps
+// their results bitwise identical.
+#pragma clang fp contract(off)
+
 namespace rlbm {
 
 // ---------------------------------------------------------------------------
@@ -130,22 +136,18 @@ struct InterpW {
     }
 };
 
-template <class S, class St, int SM, class T>
-__device__ __forceinline__ void stream_pull(const char* const (&rows)[3],
-                                            const uint32_t (&cols)[3], const InterpW<T>& W,
-                                            T (&f)[St::Q]) {
+// The interpolation itself, for any source of the 3 x 3 neighbourhood:
+// ld(q, j, i) returns population q at row y + j - 1, column x + i - 1.
+template <class St, int SM, class T, class Ld>
+__device__ __forceinline__ void stream_interp(Ld&& ld, const InterpW<T>& W, T (&f)[St::Q]) {
     constexpr bool UNIT = SM == kStreamUnit;
-    using raw = typename S::raw;
-    constexpr long long plane_bytes = kTileW * sizeof(raw);
     sfor<0, St::Q>([&](auto iq) {
         constexpr int q = decltype(iq)::value;
         constexpr Dir d = St::dir[q];
         constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
         constexpr int ux = d.cx > 0 ? 0 : (d.cx < 0 ? 2 : 1);   // upstream column index
         constexpr int uy = d.cy > 0 ? 0 : (d.cy < 0 ? 2 : 1);   // upstream row index
-        auto L = [&](int j, int i) -> T {
-            return (T)S::ld((gp<const raw>)(rows[j] + (long long)q * plane_bytes + cols[i]));
-        };
+        auto L = [&](int j, int i) -> T { return ld(q, j, i); };
         if constexpr (d.cx == 0 && d.cy == 0) {
             f[q] = L(1, 1);
         } else if constexpr (d.cy == 0) {
@@ -159,6 +161,21 @@ __device__ __forceinline__ void stream_pull(const char* const (&rows)[3],
             f[q] = fma(W.w11[n - 1], L(uy, ux), fma(W.w10[n - 1], s, W.w00[n - 1] * L(1, 1)));
         }
     });
+}
+
+// from global memory: rows[j] row y + j - 1 (wave-uniform), cols[i] the
+// per-lane byte offset of column x + i - 1
+template <class S, class St, int SM, class T>
+__device__ __forceinline__ void stream_pull(const char* const (&rows)[3],
+                                            const uint32_t (&cols)[3], const InterpW<T>& W,
+                                            T (&f)[St::Q]) {
+    using raw = typename S::raw;
+    constexpr long long plane_bytes = kTileW * sizeof(raw);
+    stream_interp<St, SM>(
+        [&](int q, int j, int i) -> T {
+            return (T)S::ld((gp<const raw>)(rows[j] + (long long)q * plane_bytes + cols[i]));
+        },
+        W, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,23 +318,23 @@ template <int D>
 __device__ __forceinline__ bool landau64(double E, double Jx, double Jy, double Pxx,
                                          double Pxy, double Pyy, double& eps, double& bx,
                                          double& by) {
-    const double J2 = Jx * Jx + Jy * Jy;
+    const double J2 = fma(Jx, Jx, Jy * Jy);
     const double Pxy2 = Pxy * Pxy;
-    double e = E - J2 * ((double)D / (D + 1)) * rcp64(E);
+    double e = fma(-J2 * ((double)D / (D + 1)), rcp64(E), E);
     bool ok = false;
     for (int it = 0; it < 16; ++it) {
         const double a = e + Pxx, c = e + Pyy;
         const double inv = rcp64(fma(a, c, -Pxy2));
-        bx = (c * Jx - Pxy * Jy) * inv;
-        by = (a * Jy - Pxy * Jx) * inv;
-        const double g = e - E + Jx * bx + Jy * by;
-        const double de = g * rcp64(1.0 - bx * bx - by * by);
+        bx = fma(c, Jx, -Pxy * Jy) * inv;
+        by = fma(a, Jy, -Pxy * Jx) * inv;
+        const double g = fma(Jx, bx, fma(Jy, by, e - E));
+        const double de = g * rcp64(fma(-bx, bx, fma(-by, by, 1.0)));
         e -= de;
         // converged: beta of this pass belongs to eps to within |de| ~ 1 ulp
         if (!(fabs(de) > 4e-16 * fabs(e))) { ok = true; break; }
     }
     eps = e;
-    const double b2 = bx * bx + by * by;
+    const double b2 = fma(bx, bx, by * by);
     return ok && e > 0.0 && b2 < 1.0 && isfinite(e) && isfinite(b2);
 }
 
@@ -329,14 +346,14 @@ __device__ __forceinline__ bool landau64(double E, double Jx, double Jy, double 
 template <int D>
 __device__ __forceinline__ void eq_coeffs(double eps, double bx, double by, double& A0,
                                           double& B, double& C, double& gamma) {
-    const double b2 = bx * bx + by * by;
+    const double b2 = fma(bx, bx, by * by);
     gamma = rsqrt64(1.0 - b2);
     const double g2 = gamma * gamma;
     constexpr double invD = 1.0 / D;
     const double hp = eps * ((D + 1.0) / D) * g2;     // (eps + P) gamma^2
     B = D * hp;
     C = (D * (D + 2) * 0.5) * hp;
-    A0 = hp - eps * invD - C * b2 * invD;
+    A0 = fma(-C * b2, invD, fma(-eps, invD, hp));
 }
 
 
@@ -355,16 +372,15 @@ struct SiteCtx {
     int eta_s;             // 1: relaxation time tau(eps) = tau eps^(-1/4) (constant eta/s)
 };
 
-template <class S, class St, bool FORCED, class T>
-__device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
-                                            T s1, int y, gp<char> drow, uint32_t own,
-                                            int* d_flag) {
-    using raw = typename S::raw;
+// sink(qc, v) receives population qc (a std::integral_constant) of the new
+// state, v = F_q - shift in the compute type.
+template <class S, class St, bool FORCED, class T, class Sink>
+__device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
+                                               T s1, int y, Sink&& sink, int* d_flag) {
     constexpr int D = St::D;
     const T ginv = ctx.ginv, dt = ctx.dt;
     const int K = ctx.K;
     const T* gtab = ctx.gtab;
-    constexpr long long plane_bytes = kTileW * sizeof(raw);
     // (c) moments, Landau frame in FP64
     const Moments<T> m = moments<St, FORCED>(f);
     const double E64 = (double)m.E + (double)S::shift;
@@ -423,20 +439,20 @@ __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T
             for (; k <= K; ++k) term(grow[4 * k], grow[4 * k + 1], grow[4 * k + 2], grow[4 * k + 3]);
         }
         const T E = (T)E64;
-        fa = (T)(-0.5) * dt * (Fx * m.Jx + Fy * m.Jy);
+        fa = (T)(-0.5) * dt * fma(Fx, m.Jx, Fy * m.Jy);
         fbx = dt * E * Fx;
         fby = dt * E * Fy;
-        const T Sxx = Fx * m.Rxxx + Fy * m.Rxxy;
-        const T Sxy = Fx * m.Rxxy + Fy * m.Rxyy;
-        const T Syy = Fx * m.Rxyy + Fy * m.Ryyy;
+        const T Sxx = fma(Fx, m.Rxxx, Fy * m.Rxxy);
+        const T Sxy = fma(Fx, m.Rxxy, Fy * m.Rxyy);
+        const T Syy = fma(Fx, m.Rxyy, Fy * m.Ryyy);
         const T k2f = (D == 3 ? (T)2.5 : (T)2.0) * dt;
-        Mxx = k2f * ((T)2 * Fx * m.Jx - Sxx);
-        Mxy = k2f * (Fx * m.Jy + Fy * m.Jx - Sxy);
-        Myy = k2f * ((T)2 * Fy * m.Jy - Syy);
+        Mxx = k2f * fma((T)2 * Fx, m.Jx, -Sxx);
+        Mxy = k2f * (fma(Fx, m.Jy, Fy * m.Jx) - Sxy);
+        Myy = k2f * fma((T)2 * Fy, m.Jy, -Syy);
         if constexpr (D == 3) {
             const T Rxzz = m.Jx - m.Rxxx - m.Rxyy;   // |v| = 1
             const T Ryzz = m.Jy - m.Rxxy - m.Ryyy;
-            Mzz = -k2f * (Fx * Rxzz + Fy * Ryzz);
+            Mzz = -k2f * fma(Fx, Rxzz, Fy * Ryzz);
         }
     }
 
@@ -462,22 +478,37 @@ __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T
         }
         const T ep = Ev + dfe;
         const T op = Ov + dfo;
-        const T gt = g * t;
         const T Kp = ep + op;
-        const T mp = omg + gt;
+        const T mp = fma(g, t, omg);
         sfor<0, Cl.nplus>([&](auto i) {
             constexpr int q = Cl.first + decltype(i)::value;
-            S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), fma(mp, f[q], Kp));
+            sink(std::integral_constant<int, q>{}, fma(mp, f[q], Kp));
         });
         if constexpr (Cl.nminus > 0) {
             const T Km = ep - op;
-            const T mm = omg - gt;
+            const T mm = fma(-g, t, omg);
             sfor<0, Cl.nminus>([&](auto i) {
                 constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
-                S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), fma(mm, f[q], Km));
+                sink(std::integral_constant<int, q>{}, fma(mm, f[q], Km));
             });
         }
     });
+}
+
+// ... storing into global memory: the destination row drow, byte offset own
+template <class S, class St, bool FORCED, class T>
+__device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
+                                            T s1, int y, gp<char> drow, uint32_t own,
+                                            int* d_flag) {
+    using raw = typename S::raw;
+    constexpr long long plane_bytes = kTileW * sizeof(raw);
+    update_site_to<S, St, FORCED>(
+        f, ctx, c1, s1, y,
+        [&](auto qc, T v) {
+            constexpr int q = decltype(qc)::value;
+            S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), v);
+        },
+        d_flag);
 }
 }  // namespace rlbm
 
@@ -590,7 +621,7 @@ __device__ void force_item(const RealDesc& Dsc, int local_item, int64_t step, in
         __syncthreads();
     }
     if (y < ny) {
-        const gp<T> g = (gp<T>)uni((T*)Dsc.g[(int)(step & 1)]);
+        const gp<T> g = (gp<T>)uni((T*)Dsc.g[(int)(step & 3)]);
         const size_t o = ((size_t)y * K1 + k) * 4;
         g[o + 0] = Px;
         g[o + 1] = Qx;

@@ -184,14 +184,18 @@ def test_full_size_sampled_one_step(storage, n, shell, amp, tau):
 @pytest.mark.parametrize("shape", [(96, 104), (130, 37)])
 def test_kernel_form_and_shape_do_not_change_results(storage, shape):
     """Per-site arithmetic is independent of the kernel form (tile / row
-    marching) and of the launch shape (tile height, segment length): bitwise,
-    also on a ragged lattice whose last strip is 2 columns wide."""
+    marching / two-step row marching) and of the launch shape (tile height,
+    segment length): bitwise, also on a ragged lattice whose last strip is 2
+    columns wide, over 5 steps (two pairs and one single step for the
+    two-step form)."""
     nx, ny = shape
     e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=4)
     fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
     ref = None
     for kind, param in [("tile", 1), ("tile", 2), ("tile", 4), ("tile", 8),
-                        ("march", 0), ("march", 1), ("march", 3), ("march", 16), ("march", 500)]:
+                        ("march", 0), ("march", 1), ("march", 3), ("march", 16), ("march", 500),
+                        ("march2", 0), ("march2", 1), ("march2", 3), ("march2", 16),
+                        ("march2", 500)]:
         lat = rl.Lattice(nx, ny, 0.56, storage=storage, forcing=fr)
         lat.set_kernel(kind, param)
         lat.set_state(dev(e), dev(bx), dev(by))
@@ -203,7 +207,7 @@ def test_kernel_form_and_shape_do_not_change_results(storage, shape):
             assert np.array_equal(F, ref), (kind, param)
 
 
-@pytest.mark.parametrize("kind", ["tile", "march"])
+@pytest.mark.parametrize("kind", ["tile", "march", "march2"])
 def test_both_kernel_forms_match_oracle(kind):
     """Random populations on a ragged lattice, forced, cfl < 1, both forms."""
     nx, ny = 67, 13
@@ -211,7 +215,7 @@ def test_both_kernel_forms_match_oracle(kind):
     force = dict(amplitude=3e-3, k_lo=1.0, k_hi=3.0, seed=8)
     lat = rl.Lattice(nx, ny, 0.6, storage="F64", cfl=0.9,
                      forcing=rl.Forcing(3e-3, 1.0, 3.0, 8))
-    lat.set_kernel(kind, 4 if kind == "march" else 2)
+    lat.set_kernel(kind, 2 if kind == "tile" else 4)
     lat.set_populations(dev(oracle_to_lib(F0)))
     lat.step(2)
     F2 = lib_to_oracle(host(lat.populations()))
@@ -238,6 +242,41 @@ def test_graph_replay_matches_direct_launches():
         torch.cuda.synchronize()
         assert np.array_equal(host(a.populations()), host(b.populations())), rep
         assert a.steps == b.steps == 8 * (rep + 1)
+    del junk
+
+
+@pytest.mark.parametrize("chunk", [4, 5])
+def test_two_step_form_graph_replay_and_checkpoint(chunk):
+    """The two-step form through captured graphs of even and odd step
+    counts, and a checkpoint taken between pairs, against one-step launches
+    of the tile form: bitwise."""
+    import torch
+    n = 96
+    e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=6)
+    fr = rl.Forcing(1e-4, 3.0, 6.0, 9)
+    a = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    b = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    a.set_kernel("tile", 4)
+    b.set_kernel("march2", 0)
+    for lat in (a, b):
+        lat.set_state(dev(e), dev(bx), dev(by))
+    b.set_graph_chunk(chunk)
+    for rep in range(3):
+        a.step(2 * chunk + 1)
+        b.step(2 * chunk + 1)      # two graph replays and one single step
+        junk = torch.randn(1000, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(a.populations()), host(b.populations())), rep
+    blob = b.save()
+    b.step(7)
+    c = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    c.set_kernel("march2", 3)
+    c.load(blob)
+    c.step(7)
+    a.step(7)
+    assert np.array_equal(host(c.populations()), host(b.populations()))
+    assert np.array_equal(host(a.populations()), host(b.populations()))
+    assert b.check() == rl.OK
     del junk
 
 
@@ -339,13 +378,17 @@ def test_circ8_parity():
     assert rel(F2, F2o) < 1e-13
 
 
-def test_ensemble_matches_oracle():
+@pytest.mark.parametrize("kind", ["auto", "march2"])
+def test_ensemble_matches_oracle(kind):
     """Independent lattices of different sizes and tau in one persistent
-    launch per step; realization r draws its force with counter word r."""
+    launch per step (or per pair of steps); realization r draws its force
+    with counter word r."""
     sizes = [(64, 64), (128, 64), (64, 128), (96, 40)]
     taus = [0.55, 0.7, 0.61, 0.8]
     frs = [rl.Forcing(1e-4, 2.0, 4.0, r) for r in range(4)]
     ens = rl.Ensemble(sizes, taus, storage="F64", forcings=frs)
+    if kind != "auto":
+        ens.set_kernel(kind, 5)
     inits = []
     for r, (nx, ny) in enumerate(sizes):
         e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=r)
