@@ -252,11 +252,11 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         population is read and written once per two steps;
  *                         param as for RLBM_KERNEL_MARCH.  An odd step count
  *                         ends with one launch of the one-step form.
- * By default the library advances pairs of steps with RLBM_KERNEL_MARCH2 when
- * the storage is not FP64 and every resident wavefront gets a segment of at
- * least 16 rows; one-step launches use RLBM_KERNEL_MARCH (param 0) for FP32
- * storage when every resident wavefront gets a segment of at least 8 rows,
- * RLBM_KERNEL_TILE with th = 4 otherwise.  With cfl > 1 only the tile form
+ * By default the library uses RLBM_KERNEL_MARCH (param 0) for FP32 storage
+ * when every resident wavefront gets a segment of at least 8 rows, and
+ * RLBM_KERNEL_TILE with th = 4 otherwise; RLBM_KERNEL_MARCH2 is used only
+ * when requested (it moves half the bytes per step but, holding two steps'
+ * rows in registers, runs fewer wavefronts and was measured slower).  With cfl > 1 only the tile form
  * exists (the marching forms give EUNSUPPORTED).  rlbm_set_tile(th) is
  * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_get_kernel reports the form
  * that advances the bulk of the steps.  rlbm_autotune times the tile

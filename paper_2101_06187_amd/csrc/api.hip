@@ -210,13 +210,13 @@ struct Engine {
         return w;
     }
 
-    // Default forms (measured on MI355X): one-step launches use the
-    // row-marching kernel when every wavefront gets a strip segment of at
-    // least 8 rows with FP32 storage, the tile kernel otherwise (small
-    // lattices, FP64, 16-bit storage); pairs of steps use the two-step
-    // marching kernel when every wavefront gets a segment of at least
-    // kPairMinRows rows (storage other than FP64, cfl <= 1).
-    static constexpr int kPairMinRows = 16;
+    // Default forms (measured on MI355X): the row-marching kernel when every
+    // wavefront gets a strip segment of at least 8 rows with FP32 storage,
+    // the tile kernel otherwise (small lattices, FP64, 16-bit storage).  The
+    // two-step marching kernel halves the memory traffic but holds both
+    // steps' rows in registers (about 220 VGPRs, 2 wavefronts per SIMD) and
+    // was measured 1.2x (2048^2) to 1.8x (8192^2) slower per step than the
+    // one-step forms, so it is used only when requested.
     void choose_kind() {
         if (!kind_auto) return;
         Cfg& c = cfg[0];
@@ -226,9 +226,7 @@ struct Engine {
         c.kind = (storage == RLBM_F32 && long_segments && smode != kStreamHalo2) ? kKernelMarch
                                                                                 : kKernelTile;
         c.seglen_req = 0;
-        const long long waves2 = (long long)cus * occupancy(kKernelMarch2, 4) * 4;
-        pairs = storage != RLBM_F64 && smode != kStreamHalo2 &&
-                wave_rows(kTileW - 2) >= kPairMinRows * std::max(1LL, waves2);
+        pairs = false;
         cfg[1].kind = kKernelMarch2;
         cfg[1].th = 4;
         cfg[1].seglen_req = 0;
@@ -244,9 +242,19 @@ struct Engine {
         const int width = c.kind == kKernelMarch2 ? kTileW - 2 : kTileW;
         int seg = c.seglen_req;
         if (c.kind != kKernelTile && seg <= 0) {
-            // about one strip segment per resident wavefront, at least 2 rows
+            // about one strip segment per resident wavefront, at least 2 rows,
+            // and no more segments than resident wavefronts (a few too many
+            // would take a second round of the whole grid)
             const long long target = std::max(1LL, (long long)slots * 4);
             seg = (int)std::max(2LL, (wave_rows(width) + target - 1) / target);
+            auto units = [&](int sl) {
+                long long n = 0;
+                for (int r = 0; r < n_real; ++r)
+                    n += (long long)((hdesc[r].nx + width - 1) / width) *
+                         ((hdesc[r].ny + sl - 1) / sl);
+                return n;
+            };
+            while (units(seg) > target && seg < 65536) ++seg;
         }
         c.seglen = c.kind == kKernelTile ? c.th : seg;
         c.n_tiles = 0;

@@ -573,8 +573,8 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
 
         // step-s rows r0 .. r1 feed the outputs ya .. yb - 1
         const int r0 = ya - 1, r1 = yb;
-        T cur[Q], pre[Q], up[M::nU], dn[M::nD];   // input window (as march_kernel)
-        T sc[Q], su[M::nU];                       // step-s rows r - 1 (all), r - 2 (c_y > 0)
+        T cur[Q], up[M::nU], dn[M::nD];           // input rows rr, rr - 1, rr + 1
+        T sc[Q], su[M::nU];                       // step-s rows rr - 1 (all), rr - 2 (c_y > 0)
         sfor<0, Q>([&](auto iq) {
             constexpr int q = decltype(iq)::value;
             cur[q] = ld(q, r0);
@@ -583,16 +583,9 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         });
         T hp = gather(r0 - 1);
         T hc = gather(r0);
-        T hn = 0;
+        T hn = gather(r0 + 1);
 
         for (int rr = r0; rr <= r1; ++rr) {
-            if (rr < r1) {                       // next input row in flight
-                sfor<0, Q>([&](auto iq) {
-                    constexpr int q = decltype(iq)::value;
-                    pre[q] = ld(q, M::cy(q) < 0 ? rr + 2 : rr + 1);
-                });
-                hn = gather(rr + 1);
-            }
             // step s at row rr, every lane
             T f[Q];
             sfor<0, Q>([&](auto iq) {
@@ -625,6 +618,25 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                     }
                 }
             });
+            // the input window moves down one row now: its loads are in
+            // flight while the second step below is computed
+            if (rr < r1) {
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    if constexpr (M::cy(q) > 0) {
+                        up[M::uidx(q)] = cur[q];
+                        cur[q] = ld(q, rr + 1);
+                    } else if constexpr (M::cy(q) < 0) {
+                        cur[q] = dn[M::didx(q)];
+                        dn[M::didx(q)] = ld(q, rr + 2);
+                    } else {
+                        cur[q] = ld(q, rr + 1);
+                    }
+                });
+                hp = hc;
+                hc = hn;
+                hn = gather(rr + 2);
+            }
             T fn[Q];
             update_site_to<S, St, FORCED>(
                 f, c0, cs, sn, wrap(rr),
@@ -669,23 +681,12 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                                                (gp<char>)(dst + (long long)(rr - 1) * rowq), colb,
                                                A.d_flag);
             }
-            // roll the step-s window and the input window
+            // roll the step-s window
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
                 if constexpr (M::cy(q) > 0) su[M::uidx(q)] = sc[q];
                 sc[q] = fn[q];
-                if constexpr (M::cy(q) > 0) {
-                    up[M::uidx(q)] = cur[q];
-                    cur[q] = pre[q];
-                } else if constexpr (M::cy(q) < 0) {
-                    cur[q] = dn[M::didx(q)];
-                    dn[M::didx(q)] = pre[q];
-                } else {
-                    cur[q] = pre[q];
-                }
             });
-            hp = hc;
-            hc = hn;
         }
     }
 
