@@ -12,7 +12,6 @@
 namespace rlbm {
 
 constexpr int kTileW = 64;            // sites per tile row = one wavefront
-constexpr int kMaxTileH = 8;
 
 // Work decomposition of one lattice for one launch configuration.
 struct WorkMap {

@@ -2,16 +2,21 @@
 // stirring force of Sec. III C / App. B), one translation unit per storage
 // form, selected by RLBM_STORAGE_ID at compile time.
 //
-// One thread owns one lattice site.  A block is a tile of 64 x th sites (one
-// wavefront per tile row).  The grid is persistent: block b walks the tiles of
-// the chunk that belongs to its XCD (b mod 8), so horizontally and vertically
-// adjacent tiles -- which share halo cache lines -- are served by the same L2.
-// Per site, in registers:
+// Three forms of the same per-site update (update_site in site.hpp):
+//   step_kernel   -- one thread owns one lattice site; a block is a tile of
+//                    64 x th sites (one wavefront per tile row);
+//   march_kernel  -- a wavefront marches down a 64-column strip segment with a
+//                    rolling register window of rows;
+//   march2_kernel -- the same for two time steps per launch.
+// Grids are persistent: block b walks the work items of the chunk that belongs
+// to its XCD (b mod 8), so adjacent tiles -- which share halo cache lines --
+// are served by the same L2.  Per site, in registers:
 //   stream (pull, bilinear)  ->  moments  ->  FP64 Landau frame  ->
 //   equilibrium coefficients ->  force field + projected force term  ->
 //   Anderson-Witting collision  ->  store.
-// Only the population loads and stores touch HBM.  After its tiles, every
-// block also builds part of the next step's force table.
+// Only the population loads and stores touch HBM.  Blocks without tiles (or,
+// when there are none, every block after its tiles) build the force tables of
+// the two steps after the launch.
 #include <hip/hip_ext.h>
 
 #include "site.hpp"
