@@ -311,8 +311,11 @@ __device__ __forceinline__ double rsqrt64(double x) {
 //     (eps I + Pi) beta = J,   eps = E - J . beta,
 // i.e. eps is the root of g(eps) = eps - E + J^T (eps I + Pi)^-1 J with
 // g'(eps) = 1 - |beta|^2 > 0.  Newton's method from the small-velocity
-// estimate eps0 = E - |J|^2 D / ((D+1) E).  Returns false if it does not
-// converge or the result is unphysical.
+// estimate eps0 = E - |J|^2 D / ((D+1) E).  Since 0 < g'' <= 2 |J|^2 / eps^3
+// and |J| <= (4/3) eps gamma^2 |beta|, a correction |de| <= 2e-8 eps leaves an
+// error below (16/9) gamma^4 beta^2 / (1 - beta^2) * 4e-16 eps (under 5e-16 eps
+// for |beta| <= 1/2): the iteration then only solves for beta at the new eps.
+// Returns false if it does not converge or the result is unphysical.
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ bool landau64(double E, double Jx, double Jy, double Pxx,
@@ -322,16 +325,24 @@ __device__ __forceinline__ bool landau64(double E, double Jx, double Jy, double 
     const double Pxy2 = Pxy * Pxy;
     double e = fma(-J2 * ((double)D / (D + 1)), rcp64(E), E);
     bool ok = false;
-    for (int it = 0; it < 16; ++it) {
-        const double a = e + Pxx, c = e + Pyy;
+    auto solve_beta = [&](double ee) {
+        const double a = ee + Pxx, c = ee + Pyy;
         const double inv = rcp64(fma(a, c, -Pxy2));
         bx = fma(c, Jx, -Pxy * Jy) * inv;
         by = fma(a, Jy, -Pxy * Jx) * inv;
+    };
+    for (int it = 0; it < 16; ++it) {
+        solve_beta(e);
         const double g = fma(Jx, bx, fma(Jy, by, e - E));
         const double de = g * rcp64(fma(-bx, bx, fma(-by, by, 1.0)));
         e -= de;
         // converged: beta of this pass belongs to eps to within |de| ~ 1 ulp
         if (!(fabs(de) > 4e-16 * fabs(e))) { ok = true; break; }
+        if (fabs(de) <= 2e-8 * fabs(e)) {
+            solve_beta(e);
+            ok = true;
+            break;
+        }
     }
     eps = e;
     const double b2 = fma(bx, bx, by * by);
@@ -402,7 +413,7 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
     double g64 = gam * (double)ginv;
     // constant eta/s (Sec. III A): tau_R = 5 (eta/s) / T with T = eps^(1/4)
     // for massless particles at T0 = 1, so 1/tau scales as eps^(1/4)
-    if (ctx.eta_s) g64 *= sqrt(sqrt(eps));
+    if (__builtin_expect(ctx.eta_s != 0, 0)) g64 *= rsqrt64(rsqrt64(eps));   // eps^(1/4)
     const T g = (T)g64;
     const T k0 = (T)(g64 * A0s), k1 = (T)(g64 * (Bd - A0s));
     const T k2 = (T)(g64 * (Cd - Bd)), k3 = (T)(g64 * Cd);
@@ -457,40 +468,69 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
     }
 
     // (e) collide + force, store:  F' <- (1 - omega) F' + omega (F_eq - shift) + dF
+    // For a member with velocity +-v, v = (m d, vz), d one of the in-plane
+    // directions X = (1, 0), Y = (0, 1), P = (1, 1), M = (1, -1) (or none), and
+    // t = beta.v = m (beta.d):
+    //   even part  k0 + fa + k2 t^2 + v.Mf.v = (k0 + fa + vz^2 Mzz) + m^2 SN_d,
+    //              SN_d = k2 (beta.d)^2 + d.Mf.d;
+    //   odd part   t k1 - k3 t^3 + v.fb     = m (PN_d - k3 m^2 (beta.d)^3),
+    //              PN_d = k1 (beta.d) + d.fb;
+    //   rate       omega = g (1 - t), so 1 - omega = omg + g m (beta.d).
+    // The direction quantities are formed once per site; a class costs a few
+    // fused multiply-adds.
+    T tn[4] = {bx, by, bx + by, bx - by};
+    T SN[4], PN[4], tn3[4];
+    T dM[4] = {0, 0, 0, 0}, dfb[4] = {0, 0, 0, 0};
+    T k0e = k0, eh = k0, et = k0, ez = k0;   // k0 + fa + vz^2 Mzz for vz^2 = 0, 1/2, 1/3, 1
+    if constexpr (FORCED) {
+        const T dxy = Mxx + Myy;
+        dM[0] = Mxx; dM[1] = Myy;
+        dM[2] = fma((T)2, Mxy, dxy); dM[3] = fma((T)-2, Mxy, dxy);
+        dfb[0] = fbx; dfb[1] = fby; dfb[2] = fbx + fby; dfb[3] = fbx - fby;
+        k0e = k0 + fa;
+        eh = fma((T)0.5, Mzz, k0e);
+        et = fma((T)(1.0 / 3.0), Mzz, k0e);
+        ez = k0e + Mzz;
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const T t2 = tn[d] * tn[d];
+        tn3[d] = t2 * tn[d];
+        SN[d] = fma(k2, t2, dM[d]);
+        PN[d] = fma(k1, tn[d], dfb[d]);
+    }
+    const T k3m[3] = {k3, k3 * (T)0.5, k3 * (T)(1.0 / 3.0)};                 // k3 m^2
+    const T gm[3] = {g, g * (T)kInvSqrt2, g * (T)kInvSqrt3};                // g m
     sfor<0, St::NC>([&](auto ic) {
         constexpr DirClass Cl = St::cls[ic];
-        constexpr double um = comp_mag(Cl.ncomp);
-        constexpr double ux = Cl.sx * um, uy = Cl.sy * um;
-        T t = 0;
-        if constexpr (ux != 0.0) t = (T)ux * bx;
-        if constexpr (uy != 0.0) t = fma((T)uy, by, t);
-        const T t2 = t * t;
-        const T Ev = fma(k2, t2, k0);
-        const T Ov = t * fma(-k3, t2, k1);
-        T dfe = fa, dfo = 0;
-        if constexpr (FORCED) {
-            if constexpr (ux != 0.0) dfe = fma((T)(ux * ux), Mxx, dfe);
-            if constexpr (ux != 0.0 && uy != 0.0) dfe = fma((T)(2.0 * ux * uy), Mxy, dfe);
-            if constexpr (uy != 0.0) dfe = fma((T)(uy * uy), Myy, dfe);
-            if constexpr (Cl.vz2 != 0.0) dfe = fma((T)Cl.vz2, Mzz, dfe);
-            if constexpr (ux != 0.0) dfo = (T)ux * fbx;
-            if constexpr (uy != 0.0) dfo = fma((T)uy, fby, dfo);
-        }
-        const T ep = Ev + dfe;
-        const T op = Ov + dfo;
-        const T Kp = ep + op;
-        const T mp = fma(g, t, omg);
-        sfor<0, Cl.nplus>([&](auto i) {
-            constexpr int q = Cl.first + decltype(i)::value;
-            sink(std::integral_constant<int, q>{}, fma(mp, f[q], Kp));
-        });
-        if constexpr (Cl.nminus > 0) {
-            const T Km = ep - op;
-            const T mm = fma(-g, t, omg);
-            sfor<0, Cl.nminus>([&](auto i) {
-                constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
-                sink(std::integral_constant<int, q>{}, fma(mm, f[q], Km));
+        static_assert(Cl.sx >= 0, "class directions are listed with c_x >= 0");
+        constexpr int di = Cl.sx != 0 ? (Cl.sy == 0 ? 0 : (Cl.sy > 0 ? 2 : 3)) : (Cl.sy != 0 ? 1 : -1);
+        constexpr int mi = Cl.ncomp - 1;
+        constexpr double m = comp_mag(Cl.ncomp);
+        const T e0 = Cl.vz2 == 0.0 ? k0e : (Cl.vz2 == 0.5 ? eh : (Cl.vz2 == 1.0 ? ez : et));
+        if constexpr (di < 0) {
+            // v = (0, 0, +-1): t = 0, no odd part, rate omega = g
+            sfor<0, Cl.nplus>([&](auto i) {
+                constexpr int q = Cl.first + decltype(i)::value;
+                sink(std::integral_constant<int, q>{}, fma(omg, f[q], e0));
             });
+        } else {
+            const T ep = fma((T)(m * m), SN[di], e0);
+            const T op = (T)m * fma(-k3m[mi], tn3[di], PN[di]);
+            const T Kp = ep + op;
+            const T mp = fma(gm[mi], tn[di], omg);
+            sfor<0, Cl.nplus>([&](auto i) {
+                constexpr int q = Cl.first + decltype(i)::value;
+                sink(std::integral_constant<int, q>{}, fma(mp, f[q], Kp));
+            });
+            if constexpr (Cl.nminus > 0) {
+                const T Km = ep - op;
+                const T mm = fma(-gm[mi], tn[di], omg);
+                sfor<0, Cl.nminus>([&](auto i) {
+                    constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
+                    sink(std::integral_constant<int, q>{}, fma(mm, f[q], Km));
+                });
+            }
         }
     });
 }
