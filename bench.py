@@ -129,7 +129,8 @@ def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH2
 
 def run_ensemble(rl, torch, steps, warmup, chunk=20):
     """The 256-lattice ensemble (sides from {64, 128, 256}, tau in [0.51, 0.8]),
-    FP32 populations, one persistent launch per step, graph replay."""
+    FP32 populations, one persistent launch per step, graph replay; the
+    library's autotuner picks the kernel form and shape first."""
     import workloads
     spec = workloads.ensemble()
     sizes = [(n, n) for n, _ in spec]
@@ -139,6 +140,7 @@ def run_ensemble(rl, torch, steps, warmup, chunk=20):
     for r, (n, _) in enumerate(spec):
         e, bx, by = workloads.noisy_rest(n, n, 0.005, seed=r)
         ens.set_state(r, *(torch.from_numpy(a).to("cuda:0") for a in (e, bx, by)))
+    form = ens.autotune(10)
     ens.set_graph_chunk(chunk)
     ens.step(warmup)
     torch.cuda.synchronize()
@@ -153,7 +155,7 @@ def run_ensemble(rl, torch, steps, warmup, chunk=20):
     out = {"realizations": len(spec), "sites": sites, "ms_per_step": ms,
            "mlups": sites / (ms * 1e-3) / 1e6,
            "step_gbs": 2 * Q * BYTES["F32"] * sites / (ms * 1e-3) / 1e9,
-           "unstable": ens.check() != rl.OK}
+           "unstable": ens.check() != rl.OK, "kernel_form": list(form)}
     ens.close()
     return out
 

@@ -297,6 +297,7 @@ int rlbm_batch_init(rlbm_batch** out, int32_t n_real, const rlbm_lattice* lats,
 int rlbm_batch_set_state(rlbm_batch* b, int32_t r, const double* d_e,
                          const double* d_ux, const double* d_uy);
 int rlbm_batch_step(rlbm_batch* b, int64_t n);
+int rlbm_batch_step_count(const rlbm_batch* b, int64_t* h_steps);
 int rlbm_batch_check(rlbm_batch* b);
 int rlbm_batch_fields(rlbm_batch* b, int32_t r, double* d_e, double* d_ux,
                       double* d_uy, double* d_T);
@@ -304,8 +305,11 @@ int rlbm_batch_get_populations(rlbm_batch* b, int32_t r, double* d_out);
 int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk);
 /* rlbm_set_relaxation for every lattice of the ensemble.                   */
 int rlbm_batch_set_relaxation(rlbm_batch* b, int32_t mode);
-/* rlbm_set_kernel for the ensemble's launches.                             */
+/* rlbm_set_kernel, rlbm_get_kernel and rlbm_autotune for the ensemble's
+ * launches (the autotuner advances every lattice by the steps it times).   */
 int rlbm_batch_set_kernel(rlbm_batch* b, int32_t kind, int32_t param);
+int rlbm_batch_get_kernel(const rlbm_batch* b, int32_t* h_kind, int32_t* h_param);
+int rlbm_batch_autotune(rlbm_batch* b, int32_t steps, int32_t* h_th);
 void rlbm_batch_destroy(rlbm_batch* b);
 
 #ifdef __cplusplus

@@ -105,6 +105,9 @@ SIGNATURES = [
     ("rlbm_batch_set_graph_chunk", _I, [_P, _I32]),
     ("rlbm_batch_set_relaxation", _I, [_P, _I32]),
     ("rlbm_batch_set_kernel", _I, [_P, _I32, _I32]),
+    ("rlbm_batch_get_kernel", _I, [_P, _P, _P]),
+    ("rlbm_batch_step_count", _I, [_P, _P]),
+    ("rlbm_batch_autotune", _I, [_P, _I32, _P]),
     ("rlbm_batch_destroy", None, [_P]),
 ]
 
@@ -309,9 +312,11 @@ class Lattice:
         return _KERNEL_NAMES[k.value], p.value
 
     def autotune(self, steps=20):
+        """Time every kernel form for `steps` steps (advancing the state) and
+        keep the fastest; returns the form as kernel() does."""
         th = ctypes.c_int32()
         _check(lib().rlbm_autotune(self._ctx, int(steps), ctypes.byref(th)))
-        return th.value
+        return self.kernel()
 
     def set_graph_chunk(self, chunk):
         _check(lib().rlbm_set_graph_chunk(self._ctx, int(chunk)))
@@ -400,6 +405,24 @@ class Ensemble:
 
     def set_kernel(self, kind, param=0):
         _check(lib().rlbm_batch_set_kernel(self._b, KERNELS[kind], int(param)))
+
+    def kernel(self):
+        k, p = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rlbm_batch_get_kernel(self._b, ctypes.byref(k), ctypes.byref(p)))
+        return _KERNEL_NAMES[k.value], p.value
+
+    @property
+    def steps(self):
+        s = ctypes.c_int64()
+        _check(lib().rlbm_batch_step_count(self._b, ctypes.byref(s)))
+        return s.value
+
+    def autotune(self, steps=20):
+        """Time every kernel form for `steps` steps (advancing the state) and
+        keep the fastest; returns the form as kernel() does."""
+        th = ctypes.c_int32()
+        _check(lib().rlbm_batch_autotune(self._b, int(steps), ctypes.byref(th)))
+        return self.kernel()
 
     def close(self):
         if self._b:

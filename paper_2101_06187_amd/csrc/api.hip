@@ -1049,10 +1049,8 @@ int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param) {
 
 int rlbm_set_tile(rlbm_ctx* ctx, int32_t th) { return rlbm_set_kernel(ctx, RLBM_KERNEL_TILE, th); }
 
-int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param) {
-    if (int rc = check_ctx(ctx)) return rc;
+int engine_get_kernel(const Engine& E, int32_t* h_kind, int32_t* h_param) {
     if (!h_kind || !h_param) return fail(RLBM_EINVAL, "NULL output");
-    const Engine& E = ctx->e;
     if (E.pairs) {
         *h_kind = RLBM_KERNEL_MARCH2;
         *h_param = E.cfg[1].seglen;
@@ -1066,10 +1064,10 @@ int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param) {
     return RLBM_OK;
 }
 
-int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
-    if (int rc = check_ctx(ctx)) return rc;
+// Time every candidate form for `steps` steps (advancing the state, which no
+// form changes: results are bitwise the same) and keep the fastest.
+int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     if (steps < 1) return fail(RLBM_EINVAL, "steps must be >= 1");
-    Engine& E = ctx->e;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1082,20 +1080,23 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
                             {RLBM_KERNEL_TILE, 8},  {RLBM_KERNEL_MARCH, 0}, {RLBM_KERNEL_MARCH, -1},
                             {RLBM_KERNEL_MARCH2, 0}, {RLBM_KERNEL_MARCH2, -1}};
     int auto_seg[3] = {0, 0, 0};
+    int rc = RLBM_OK;
     for (const auto& c : cand) {
         if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
         const int param = c[1] >= 0 ? c[1] : std::max(2, 2 * auto_seg[c[0]]);
-        if (int rc = rlbm_set_kernel(ctx, c[0], param)) return rc;
+        if ((rc = engine_set_kernel(E, c[0], param))) break;
         int32_t k = 0, p = 0;
-        rlbm_get_kernel(ctx, &k, &p);
+        engine_get_kernel(E, &k, &p);
         if (c[1] == 0) auto_seg[c[0]] = p;
-        if (int rc = E.run(2)) return rc;
-        HIPCHK(hipEventRecord(e0, E.stream));
-        if (int rc = E.run(steps)) return rc;
-        HIPCHK(hipEventRecord(e1, E.stream));
-        HIPCHK(hipEventSynchronize(e1));
+        if ((rc = E.run(2))) break;
+        if (hipEventRecord(e0, E.stream) != hipSuccess) { rc = fail(RLBM_EHIP, "event record failed"); break; }
+        if ((rc = E.run(steps))) break;
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (hipEventRecord(e1, E.stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(RLBM_EHIP, "event timing failed");
+            break;
+        }
         if (ms < best) {
             best = ms;
             best_kind = k;
@@ -1104,8 +1105,19 @@ int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc) return rc;
     if (h_th) *h_th = best_kind == RLBM_KERNEL_TILE ? best_param : -best_param;
-    return rlbm_set_kernel(ctx, best_kind, best_param);
+    return engine_set_kernel(E, best_kind, best_param);
+}
+
+int rlbm_autotune(rlbm_ctx* ctx, int32_t steps, int32_t* h_th) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return engine_autotune(ctx->e, steps, h_th);
+}
+
+int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param) {
+    if (int rc = check_ctx(ctx)) return rc;
+    return engine_get_kernel(ctx->e, h_kind, h_param);
 }
 
 int rlbm_set_graph_chunk(rlbm_ctx* ctx, int32_t chunk) {
@@ -1192,6 +1204,23 @@ int rlbm_batch_set_graph_chunk(rlbm_batch* b, int32_t chunk) {
 int rlbm_batch_set_kernel(rlbm_batch* b, int32_t kind, int32_t param) {
     if (int rc = check_ctx(b)) return rc;
     return engine_set_kernel(b->e, kind, param);
+}
+
+int rlbm_batch_step_count(const rlbm_batch* b, int64_t* h_steps) {
+    if (int rc = check_ctx(b)) return rc;
+    if (!h_steps) return fail(RLBM_EINVAL, "NULL output");
+    *h_steps = b->e.step;
+    return RLBM_OK;
+}
+
+int rlbm_batch_get_kernel(const rlbm_batch* b, int32_t* h_kind, int32_t* h_param) {
+    if (int rc = check_ctx(b)) return rc;
+    return engine_get_kernel(b->e, h_kind, h_param);
+}
+
+int rlbm_batch_autotune(rlbm_batch* b, int32_t steps, int32_t* h_th) {
+    if (int rc = check_ctx(b)) return rc;
+    return engine_autotune(b->e, steps, h_th);
 }
 
 int rlbm_batch_set_relaxation(rlbm_batch* b, int32_t mode) {

@@ -280,6 +280,40 @@ def test_two_step_form_graph_replay_and_checkpoint(chunk):
     del junk
 
 
+def test_autotune_keeps_results_bitwise():
+    """The autotuner (lattice and ensemble) tries every form while stepping;
+    the state after it equals plain tile-form stepping by the same count."""
+    n = 160
+    e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=3)
+    fr = rl.Forcing(1e-4, 2.0, 5.0, 4)
+    lat = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    form = lat.autotune(3)
+    say("autotuned", form, "after", lat.steps, "steps")
+    assert form[0] in rl.KERNELS
+    ref = rl.Lattice(n, n, 0.6, storage="F32", forcing=fr)
+    ref.set_kernel("tile", 4)
+    ref.set_state(dev(e), dev(bx), dev(by))
+    ref.step(lat.steps)
+    lat.step(5)
+    ref.step(5)
+    assert np.array_equal(host(lat.populations()), host(ref.populations()))
+    sizes = [(64, 64), (96, 40)]
+    frs = [rl.Forcing(1e-4, 2.0, 4.0, r) for r in range(2)]
+    ens = rl.Ensemble(sizes, [0.6, 0.7], storage="F32", forcings=frs)
+    singles = [rl.Lattice(nx, ny, t, storage="F32", forcing=rl.Forcing(1e-4, 2.0, 4.0, 0))
+               for (nx, ny), t in zip(sizes, [0.6, 0.7])]
+    for r, (nx, ny) in enumerate(sizes):
+        e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=r)
+        ens.set_state(r, dev(e), dev(bx), dev(by))
+        if r == 0:
+            singles[0].set_state(dev(e), dev(bx), dev(by))
+    form = ens.autotune(3)
+    say("ensemble autotuned", form, "after", ens.steps, "steps")
+    singles[0].step(ens.steps)
+    assert np.array_equal(host(ens.populations(0)), host(singles[0].populations()))
+
+
 def test_checkpoint_resume_is_bitwise():
     n = 64
     e, bx, by = workloads.noisy_rest(n, n, 0.01, seed=8)
