@@ -1,0 +1,125 @@
+"""Edge cases of the GPU path against the oracle or against exact expectations:
+zero steps, the rest state, the largest lattice side the ABI accepts, fast
+flows (many Newton passes in the Landau solve), tau close to 1/2, a forcing
+shell that holds no lattice mode, a one-lattice ensemble."""
+import numpy as np
+import pytest
+
+import paper_2101_06187_amd as rl
+from oracle import diagnostics as odiag
+from oracle import rlbm as orlbm
+from oracle import stencil as ostencil
+import workloads
+
+from gpu_helpers import dev, field_errors, gpu_fields, host, lib_to_oracle, oracle_to_lib, rel, say
+
+pytestmark = pytest.mark.gpu
+
+SPH = ostencil.sph26()
+
+
+@pytest.mark.parametrize("kind", ["tile", "march", "march2"])
+def test_zero_steps_change_nothing(kind):
+    e, bx, by = workloads.noisy_rest(40, 70, 0.01, seed=1)
+    lat = rl.Lattice(70, 40, 0.6, storage="F32", forcing=rl.Forcing(1e-4, 2, 4, 1))
+    lat.set_kernel(kind, 2 if kind == "tile" else 0)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    F0 = host(lat.populations())
+    lat.step(0)
+    assert lat.steps == 0
+    assert np.array_equal(host(lat.populations()), F0)
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32", "F16S"])
+def test_rest_state_stays_stationary(storage):
+    """eps = 1, beta = 0 everywhere, unforced: every population stays at its
+    equilibrium value to rounding (the equilibrium of eps = 1 is 1 up to the
+    last bit of A0), and beta stays exactly zero (plus and minus members of
+    every class remain equal, so the momentum sums cancel exactly)."""
+    n = 48
+    lat = rl.Lattice(n, n, 0.51, storage=storage)
+    one, zero = np.ones((n, n)), np.zeros((n, n))
+    lat.set_state(dev(one), dev(zero), dev(zero))
+    F0 = host(lat.populations())
+    lat.step(25)
+    F1 = host(lat.populations())
+    say("rest drift", storage, np.abs(F1 - F0).max())
+    assert np.abs(F1 - F0).max() <= 1e-15
+    _, ux, uy, _ = gpu_fields(lat)
+    assert np.abs(ux).max() == 0.0 and np.abs(uy).max() == 0.0
+
+
+@pytest.mark.parametrize("shape", [(65536, 2), (2, 65536), (65536, 3)])
+def test_longest_side_one_step(shape):
+    """The largest side the ABI accepts (65536), against a side of 2 or 3:
+    random populations, one step of every form, against the oracle."""
+    nx, ny = shape
+    F0 = workloads.random_populations(SPH.v, ny, nx, seed=nx + ny, spread=0.3)
+    F1o = orlbm.step(F0, SPH, 0.7, 0.9)
+    for kind in ("tile", "march"):
+        lat = rl.Lattice(nx, ny, 0.7, storage="F64", cfl=0.9)
+        lat.set_kernel(kind, 2 if kind == "tile" else 0)
+        lat.set_populations(dev(oracle_to_lib(F0)))
+        lat.step(1)
+        err = rel(lib_to_oracle(host(lat.populations())), F1o)
+        say("longest side", shape, kind, err)
+        assert err < 1e-13
+        lat.close()
+
+
+def test_fast_flow_landau():
+    """Populations with a strong one-sided momentum (|beta| up to ~0.5): the
+    Landau solve takes several Newton passes; one step against the oracle."""
+    nx, ny = 40, 24
+    F = workloads.random_populations(SPH.v, ny, nx, seed=9, spread=0.1)
+    boost = 1.0 + 1.2 * SPH.v[:, 0]              # more energy moving along +x
+    F = F * boost[:, None, None]
+    _, bx, by, _ = odiag.fields(F, SPH, 1.0)
+    say("max |beta| of the input", np.hypot(bx, by).max())
+    assert np.hypot(bx, by).max() > 0.3
+    F1o = orlbm.run(F, SPH, 0.8, 2)
+    lat = rl.Lattice(nx, ny, 0.8, storage="F64")
+    lat.set_populations(dev(oracle_to_lib(F)))
+    lat.step(2)
+    assert rel(lib_to_oracle(host(lat.populations())), F1o) < 1e-13
+    assert lat.check() == rl.OK
+
+
+def test_tau_close_to_half():
+    """tau = 0.5001 (viscosity nearly zero, over-relaxation omega ~ 2): 5 steps
+    of the forced 128^2 workload against the oracle."""
+    n, tau = 128, 0.5001
+    e, bx, by = workloads.noisy_rest(n, n, 0.002, seed=4)
+    force = dict(amplitude=1e-5, k_lo=2.0, k_hi=4.0, seed=3)
+    lat = rl.Lattice(n, n, tau, storage="F64", forcing=rl.Forcing(1e-5, 2.0, 4.0, 3))
+    lat.set_state(dev(e), dev(bx), dev(by))
+    lat.step(5)
+    Fo = orlbm.run(orlbm.set_state(e, bx, by, SPH), SPH, tau, 5, force=force)
+    errs = field_errors(gpu_fields(lat), odiag.fields(Fo, SPH, 1.0))
+    say("tau 0.5001", errs)
+    assert max(errs.values()) < 1e-12
+
+
+def test_forcing_shell_without_modes_is_unforced():
+    """The shell 1.1 <= |k| <= 1.2 holds no integer wave vector: the lattice
+    evolves exactly as an unforced one."""
+    assert len(rl.forcing_modes(64, 64, rl.Forcing(1e-3, 1.1, 1.2, 5))) == 0
+    e, bx, by = workloads.noisy_rest(64, 64, 0.01, seed=2)
+    a = rl.Lattice(64, 64, 0.6, storage="F32", forcing=rl.Forcing(1e-3, 1.1, 1.2, 5))
+    b = rl.Lattice(64, 64, 0.6, storage="F32")
+    for lat in (a, b):
+        lat.set_state(dev(e), dev(bx), dev(by))
+        lat.step(6)
+    assert np.array_equal(host(a.populations()), host(b.populations()))
+
+
+def test_one_lattice_ensemble_equals_lattice():
+    e, bx, by = workloads.noisy_rest(72, 56, 0.01, seed=6)
+    fr = rl.Forcing(1e-4, 2.0, 4.0, 0)
+    ens = rl.Ensemble([(56, 72)], [0.62], storage="F32", forcings=[fr])
+    lat = rl.Lattice(56, 72, 0.62, storage="F32", forcing=fr)
+    ens.set_state(0, dev(e), dev(bx), dev(by))
+    lat.set_state(dev(e), dev(bx), dev(by))
+    ens.step(7)
+    lat.step(7)
+    assert np.array_equal(host(ens.populations(0)), host(lat.populations()))
