@@ -132,7 +132,7 @@ int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storag
         P.buf1 = off; off = align_up(off + plane * Q * s);
         P.twx = off; off = align_up(off + cs * 2 * lats[r].nx);
         P.twy = off; off = align_up(off + cs * 2 * lats[r].ny);
-        const size_t g = (size_t)lats[r].ny * (mts[r].K + 1) * 4;
+        const size_t g = (size_t)lats[r].ny * (mts[r].K + 1) * 4 + kTableSlack;
         for (int k = 0; k < 4; ++k) { P.g[k] = off; off = align_up(off + cs * g); }
         P.modes = off; off = align_up(off + sizeof(int4) * mts[r].modes.size());
         P.kptr = off; off = align_up(off + sizeof(int) * mts[r].kptr.size());

@@ -12,6 +12,7 @@
 namespace rlbm {
 
 constexpr int kTileW = 64;            // sites per tile row = one wavefront
+constexpr int kTableSlack = 32;       // compute-type values after the last row of a force table
 
 // Work decomposition of one lattice for one launch configuration.
 struct WorkMap {
@@ -29,7 +30,8 @@ struct RealDesc {
     const void* twx;              // [nx][2] cos, sin of 2 pi x / nx (compute type)
     const void* twy;              // [ny][2] cos, sin of 2 pi y / ny (compute type)
     void* g[4];                   // force table of step s in g[s & 3]:
-                                  //   [ny][K+1][4] = Px, Qx, Py, Qy (compute type)
+                                  //   [ny][K+1][4] = Px, Qx, Py, Qy (compute type),
+                                  //   then kTableSlack values that are never used
     const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
     const int* kptr;              // K+2 offsets into modes
     int nx, ny;

@@ -36,6 +36,10 @@ __device__ __forceinline__ void sfor(F&& f) {
 // ---------------------------------------------------------------------------
 template <class X>
 using gp = __attribute__((address_space(1))) X*;
+// Constant address space: memory that no wave of the running kernel writes.
+// A wave-uniform address into it is read with scalar loads into SGPRs.
+template <class X>
+using kp = __attribute__((address_space(4))) X*;
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ long long uni(long long v) {
@@ -427,7 +431,10 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
         // cos/sin(k a) by the Chebyshev recurrence.
         T Fx = 0, Fy = 0;
         if (K >= 0) {                       // K < 0: this lattice is unforced
-            const gp<const T> grow = (gp<const T>)gtab + (size_t)y * (K + 1) * 4;
+            // The table row of a wave's lattice row is the same for all its lanes and
+            // was written by an earlier launch (a launch only writes the tables of
+            // later steps), so it is read as constant memory: scalar loads, no VGPRs.
+            const kp<const T> grow = (kp<const T>)gtab + (size_t)y * (K + 1) * 4;
             Fx = grow[0];
             Fy = grow[2];
             T cp = 1, sp = 0, ck = c1, sk = s1;
@@ -439,15 +446,27 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
                 const T sn = fma(two_c1, sk, -sp);
                 cp = ck; sp = sk; ck = cn; sk = sn;
             };
+            // Batches of RB table rows (32 values): one round of scalar loads per
+            // batch.  Every table buffer has kTableSlack values after its last row,
+            // so the last batch may reach past row K; those values are never used.
+            constexpr int RB = sizeof(T) == 8 ? 4 : 8;
+            static_assert(4 * (RB - 1) <= kTableSlack, "a batch may reach 4 RB - 4 values past row K");
             int k = 1;
-            for (; k + 3 <= K; k += 4) {      // four table rows per batch of loads
-                T gv[16];
+            for (; k + RB - 1 <= K; k += RB) {
+                T gv[4 * RB];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) gv[i] = grow[4 * k + i];
+                for (int i = 0; i < 4 * RB; ++i) gv[i] = grow[4 * k + i];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
+                for (int i = 0; i < RB; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
             }
-            for (; k <= K; ++k) term(grow[4 * k], grow[4 * k + 1], grow[4 * k + 2], grow[4 * k + 3]);
+            if (k <= K) {
+                T gv[4 * RB];
+#pragma unroll
+                for (int i = 0; i < 4 * RB; ++i) gv[i] = grow[4 * k + i];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    if (k + i <= K) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
+            }
         }
         const T E = (T)E64;
         fa = (T)(-0.5) * dt * fma(Fx, m.Jx, Fy * m.Jy);
