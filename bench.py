@@ -106,8 +106,25 @@ def field_error(a, b):
             "beta": float(max(np.abs(xa - xb).max(), np.abs(ya - yb).max()) / vmax)}
 
 
-def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH26"):
+def tune_form(rl, wl, storage, torch, stencil, tune_steps):
+    """The library's autotuner run on a scratch lattice of the same
+    configuration; returns the kernel form it keeps."""
+    scratch = make_lattice(rl, wl, storage, torch, stencil)
+    form = scratch.autotune(tune_steps)
+    scratch.close()
+    del scratch
+    torch.cuda.empty_cache()
+    return form
+
+
+def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH26",
+             tune_steps=0, form=None):
+    tuned = form is None and tune_steps > 0
+    if tuned:
+        form = tune_form(rl, wl, storage, torch, stencil, tune_steps)
     lat = make_lattice(rl, wl, storage, torch, stencil)
+    if form is not None:
+        lat.set_kernel(*form)
     ms = time_steps(lat, torch, steps, warmup, chunk)
     kms = lat.profile_step_kernel(prof_n)
     sites = wl.n * wl.n
@@ -124,6 +141,7 @@ def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH2
     }
     out["kernel_frac_hbm_peak"] = out["kernel_gbs"] / HBM_PEAK_GBS
     out["kernel_form"] = list(lat.kernel())
+    out["autotuned"] = tuned
     return lat, out
 
 
@@ -191,6 +209,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the HBM-resident 2048^2 / 8192^2 lines")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--tune-steps", type=int, default=None,
+                    help="steps per candidate of the library's autotuner, run on a scratch "
+                         "lattice before each form is timed (scaled down as 512/n on the "
+                         "larger lattices, at least 4; 0: the library's default form). "
+                         "Default 40, and 0 with --only")
+    ap.add_argument("--form", default=None, metavar="KIND:PARAM",
+                    help="with --only: time this kernel form (e.g. march:22 or tile:4)")
     ap.add_argument("--only", default=None, metavar="WORKLOAD:STORAGE[:STENCIL]",
                     help="time one form only (e.g. forced2048:F32 or "
                          "forced2048:F32:SPH26_ZFOLD), for profiler runs")
@@ -198,6 +223,8 @@ def main():
                     help="also run a plain device copy of this many bytes 3 times "
                          "(counter calibration under rocprofv3 --pmc)")
     a = ap.parse_args()
+    if a.tune_steps is None:
+        a.tune_steps = 0 if a.only else 40
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -223,8 +250,14 @@ def main():
     if a.only:
         name, storage, *st = a.only.split(":")
         w = workloads.WORKLOADS[name]
+        form = None
+        if a.form:
+            kind, param = a.form.split(":")
+            form = (kind, int(param))
+        tune = a.tune_steps or 0
         lat, r = run_form(rl, torch, w, storage, a.steps, a.warmup, 50, min(a.steps, 200),
-                          st[0] if st else "SPH26")
+                          st[0] if st else "SPH26",
+                          tune_steps=max(4, tune * 512 // w.n) if tune else 0, form=form)
         r["unstable"] = lat.check() != rl.OK
         log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms'] * 1e3:.2f} us "
             f"= {r['kernel_gbs']:.0f} GB/s")
@@ -236,7 +269,8 @@ def main():
     forms = {}
     lats = {}
     for storage in ("F32", "F64", "F16S", "BF16S"):
-        lat, r = run_form(rl, torch, wl, storage, a.steps, a.warmup, chunk, 500)
+        lat, r = run_form(rl, torch, wl, storage, a.steps, a.warmup, chunk, 500,
+                          tune_steps=a.tune_steps)
         lats[storage] = lat
         forms[storage] = r
         log(f"{storage}: {r['mlups']:.0f} MLUPS, {r['ms_per_step'] * 1e3:.2f} us/step, "
@@ -255,7 +289,8 @@ def main():
     # lattice): same workload, same step, fewer bytes per site.
     for storage in ("F32", "F16S"):
         key = storage + "_ZFOLD"
-        lat, r = run_form(rl, torch, wl, storage, a.steps, a.warmup, chunk, 500, "SPH26_ZFOLD")
+        lat, r = run_form(rl, torch, wl, storage, a.steps, a.warmup, chunk, 500, "SPH26_ZFOLD",
+                          tune_steps=a.tune_steps)
         r["field_error_vs_f64"] = field_error(lat.fields(), ref)
         r["unstable"] = lat.check() != rl.OK
         lat.close()
@@ -275,7 +310,9 @@ def main():
             for key in storages:
                 storage, _, fold = key.partition("_")
                 lat, r = run_form(rl, torch, w, storage, steps, 20, 20, 20,
-                                  "SPH26_ZFOLD" if fold else "SPH26")
+                                  "SPH26_ZFOLD" if fold else "SPH26",
+                                  tune_steps=max(4, a.tune_steps * 512 // w.n)
+                                  if a.tune_steps else 0)
                 r["unstable"] = lat.check() != rl.OK
                 lat.close()
                 del lat

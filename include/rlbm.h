@@ -246,6 +246,11 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         every population row once into a rolling register
  *                         window; param = rows per strip segment (0: chosen
  *                         from the lattice size and the GPU's resident waves).
+ *   RLBM_KERNEL_STAGED -- a block of 4 wavefronts stages the population rows
+ *                         of its 64 x 4 tile (its own rows, the needed
+ *                         populations of the rows above and below, and the
+ *                         halo columns) into LDS with aligned row loads, then
+ *                         every site streams from LDS; param = 4 (or 0).
  *   RLBM_KERNEL_MARCH2 -- two time steps per launch: each wavefront marches
  *                         down a 62-column strip computing the first step
  *                         into registers and the second from them, so every
@@ -260,10 +265,11 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  * exists (the marching forms give EUNSUPPORTED).  rlbm_set_tile(th) is
  * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_get_kernel reports the form
  * that advances the bulk of the steps.  rlbm_autotune times the tile
- * heights and two segment lengths of each marching form for `steps` steps
- * each (advancing the state) and keeps the fastest; *h_th receives th, or
- * minus the segment length for a marching form.                            */
-enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1, RLBM_KERNEL_MARCH2 = 2 };
+ * heights, four segment lengths of the row-marching form (the automatic one
+ * and 1/2, 3/2 and 2 times it) and two of the two-step form for `steps`
+ * steps each (advancing the state) and keeps the fastest; *h_th receives th,
+ * or minus the segment length for a marching form.                         */
+enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1, RLBM_KERNEL_MARCH2 = 2, RLBM_KERNEL_STAGED = 3 };
 int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param);
 int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param);
 int rlbm_set_tile(rlbm_ctx* ctx, int32_t th);

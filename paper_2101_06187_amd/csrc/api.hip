@@ -236,12 +236,13 @@ struct Engine {
     // two-step kernel) columns x seglen rows), their maps, the persistent grid
     int configure_map(int m) {
         Cfg& c = cfg[m];
-        if (c.kind != kKernelTile) c.th = 4;          // 4 wavefronts per block
+        if (c.kind != kKernelTile) c.th = 4;          // 4 wavefronts per block (kStageTH)
         const int per_cu = occupancy(c.kind, c.th);
         const int slots = cus * per_cu;
         const int width = c.kind == kKernelMarch2 ? kTileW - 2 : kTileW;
         int seg = c.seglen_req;
-        if (c.kind != kKernelTile && seg <= 0) {
+        const bool tiled = c.kind == kKernelTile || c.kind == kKernelStaged;
+        if (!tiled && seg <= 0) {
             // about one strip segment per resident wavefront, at least 2 rows,
             // and no more segments than resident wavefronts (a few too many
             // would take a second round of the whole grid)
@@ -256,7 +257,7 @@ struct Engine {
             };
             while (units(seg) > target && seg < 65536) ++seg;
         }
-        c.seglen = c.kind == kKernelTile ? c.th : seg;
+        c.seglen = tiled ? c.th : seg;
         c.n_tiles = 0;
         c.n_gitems = 0;
         std::vector<uint16_t> map, gmap;
@@ -281,7 +282,7 @@ struct Engine {
         if (n_real > 1 && !gmap.empty())
             HIPCHK(hipMemcpyAsync(c.d_gitems, gmap.data(), sizeof(uint16_t) * gmap.size(),
                                   hipMemcpyHostToDevice, stream));
-        const int groups = c.kind == kKernelTile ? c.n_tiles : (c.n_tiles + 3) / 4;
+        const int groups = tiled ? c.n_tiles : (c.n_tiles + 3) / 4;
         c.tile_blocks = std::max(8, std::min(groups, slots));
         // when the tiles leave resident slots free, build the next force tables
         // on extra blocks that run alongside the tiles
@@ -1022,6 +1023,13 @@ int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
         E.cfg[0].kind = kKernelTile;
         E.cfg[0].th = param;
         E.pairs = false;
+    } else if (kind == RLBM_KERNEL_STAGED) {
+        if (param != 0 && param != 4) return fail(RLBM_EINVAL, "staged tile height must be 4 (or 0)");
+        if (E.smode == kStreamHalo2)
+            return fail(RLBM_EUNSUPPORTED, "the staged form needs cfl <= 1");
+        E.cfg[0].kind = kKernelStaged;
+        E.cfg[0].th = 4;
+        E.pairs = false;
     } else if (kind == RLBM_KERNEL_MARCH || kind == RLBM_KERNEL_MARCH2) {
         if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
         if (E.smode == kStreamHalo2)
@@ -1057,6 +1065,9 @@ int engine_get_kernel(const Engine& E, int32_t* h_kind, int32_t* h_param) {
     } else if (E.cfg[0].kind == kKernelMarch) {
         *h_kind = RLBM_KERNEL_MARCH;
         *h_param = E.cfg[0].seglen;
+    } else if (E.cfg[0].kind == kKernelStaged) {
+        *h_kind = RLBM_KERNEL_STAGED;
+        *h_param = E.cfg[0].th;
     } else {
         *h_kind = RLBM_KERNEL_TILE;
         *h_param = E.cfg[0].th;
@@ -1075,15 +1086,22 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     float best = 1e30f;
     int best_kind = -1, best_param = 0;
     // (kind, parameter): tile heights; marching forms with the automatic
-    // segment length (0) and twice it (-1)
-    const int cand[8][2] = {{RLBM_KERNEL_TILE, 1},  {RLBM_KERNEL_TILE, 2},  {RLBM_KERNEL_TILE, 4},
-                            {RLBM_KERNEL_TILE, 8},  {RLBM_KERNEL_MARCH, 0}, {RLBM_KERNEL_MARCH, -1},
-                            {RLBM_KERNEL_MARCH2, 0}, {RLBM_KERNEL_MARCH2, -1}};
-    int auto_seg[3] = {0, 0, 0};
+    // segment length (0: about one segment per resident wavefront) and with
+    // segments 2x (-1), 3/2 x (-2) and 1/2 x (-3) as long; which of these runs
+    // fastest depends on how the last round of segments fills the chip
+    const int cand[11][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
+                             {RLBM_KERNEL_TILE, 4},   {RLBM_KERNEL_TILE, 8},
+                             {RLBM_KERNEL_STAGED, 4},
+                             {RLBM_KERNEL_MARCH, 0},  {RLBM_KERNEL_MARCH, -1},
+                             {RLBM_KERNEL_MARCH, -2}, {RLBM_KERNEL_MARCH, -3},
+                             {RLBM_KERNEL_MARCH2, 0}, {RLBM_KERNEL_MARCH2, -1}};
+    int auto_seg[4] = {0, 0, 0, 0};
     int rc = RLBM_OK;
     for (const auto& c : cand) {
         if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
-        const int param = c[1] >= 0 ? c[1] : std::max(2, 2 * auto_seg[c[0]]);
+        const int a = auto_seg[c[0]];
+        const int param = c[1] >= 0 ? c[1]
+                          : std::max(2, c[1] == -1 ? 2 * a : (c[1] == -2 ? (3 * a + 1) / 2 : (a + 1) / 2));
         if ((rc = engine_set_kernel(E, c[0], param))) break;
         int32_t k = 0, p = 0;
         engine_get_kernel(E, &k, &p);
@@ -1106,7 +1124,8 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if (h_th) *h_th = best_kind == RLBM_KERNEL_TILE ? best_param : -best_param;
+    if (h_th) *h_th = best_kind == RLBM_KERNEL_TILE || best_kind == RLBM_KERNEL_STAGED ? best_param
+                                                                                     : -best_param;
     return engine_set_kernel(E, best_kind, best_param);
 }
 

@@ -186,6 +186,211 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS-staged tile form.  A block of kStageTH wavefronts owns a tile of 64 x
+// kStageTH sites.  Every population row the tile needs is read from global
+// memory once, with aligned row loads, into LDS: the tile's own rows (every
+// population), the row above it (only the populations pulled from above,
+// c_y > 0) and the row below it (c_y < 0), each with the two halo columns of
+// the strip (one gathered load per row).  After a barrier every site
+// interpolates from LDS and applies the same update_site as the other forms,
+// so all forms give bitwise identical results.
+// In LDS a row is population-major, with the populations ordered by c_y
+// (c_y < 0, then c_y = 0, then c_y > 0), so the two partial halo rows take
+// only the slots they use: population q of LDS row r (lattice row y0 - 1 + r)
+// sits in slot row  r Q + slot(q) - (nD + n0), and a slot row holds kLdsW
+// values: halo column x0 - 1 at index 3, the strip's columns at 4 .. 67, the
+// right halo column right after the strip's last column.
+// ---------------------------------------------------------------------------
+constexpr int kStageTH = 4;
+constexpr int kLdsW = 72;
+
+template <class St>
+struct StageMap {
+    static constexpr int Q = St::Q;
+    static constexpr int cx(int q) { return St::dir[q].cx; }
+    static constexpr int cy(int q) { return St::dir[q].cy; }
+    static constexpr int ygroup(int q) { return cy(q) < 0 ? 0 : (cy(q) == 0 ? 1 : 2); }
+    static constexpr int count(int g) {
+        int n = 0;
+        for (int q = 0; q < Q; ++q) n += ygroup(q) == g;
+        return n;
+    }
+    static constexpr int nD = count(0), n0 = count(1), nU = count(2);
+    static constexpr int slot(int q) {
+        int k = 0;
+        for (int p = 0; p < Q; ++p)
+            k += ygroup(p) < ygroup(q) || (ygroup(p) == ygroup(q) && p < q);
+        return k;
+    }
+    static constexpr int kSlotRows = kStageTH * Q + nU + nD;
+    static constexpr int srow(int r, int q) { return r * Q + slot(q) - (nD + n0); }
+    // lanes of the halo gather: populations with c_x != 0
+    static constexpr int nH() {
+        int k = 0;
+        for (int q = 0; q < Q; ++q) k += cx(q) != 0;
+        return k;
+    }
+    static constexpr int hidx(int q) {
+        int k = 0;
+        for (int p = 0; p < q; ++p) k += cx(p) != 0;
+        return k;
+    }
+};
+
+// FP64 stages twice the bytes (two blocks per CU fit the LDS) and needs its
+// registers; the other forms are held to 128 VGPRs, so that four blocks -- one
+// tile row per SIMD each -- are resident per CU.
+template <class S>
+constexpr int stage_min_waves() { return sizeof(typename S::raw) == 8 ? 1 : 4; }
+
+template <class S, class St, int SM, bool FORCED>
+__global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_kernel(StepArgs A) {
+    static_assert(SM != kStreamHalo2, "the staged form streams from the nearest rows only");
+    using T = typename S::T;
+    using raw = typename S::raw;
+    using M = StageMap<St>;
+    constexpr int Q = St::Q;
+    constexpr int TH = kStageTH;
+    constexpr bool F64 = std::is_same<T, double>::value;
+    constexpr long long plane_bytes = kTileW * sizeof(raw);
+    __shared__ raw sm[M::kSlotRows * kLdsW];
+
+    const int64_t step = A.d_step[0] + A.step_off;
+    const int par = (int)((A.d_step[1] + A.launch_off) & 1);
+    const int lx = threadIdx.x;
+    const int w = uni((int)threadIdx.y);
+
+    // XCD-aware persistent schedule, as in step_kernel
+    const int G = A.tile_blocks;
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int nb = (G - xcd + 7) >> 3;
+    const int chunk = (A.n_tiles + 7) >> 3;
+    const int t_end = min(A.n_tiles, (xcd + 1) * chunk);
+
+    // this lane's population in the halo gather
+    int my_q = 0, my_slot = 0, my_cy = 0;
+    bool my_left = true;
+    sfor<0, Q>([&](auto iq) {
+        constexpr int q = decltype(iq)::value;
+        if constexpr (M::cx(q) != 0) {
+            if (lx == M::hidx(q)) {
+                my_q = q;
+                my_slot = M::slot(q);
+                my_cy = M::cy(q);
+                my_left = M::cx(q) > 0;
+            }
+        }
+    });
+
+    int cur_r = -1;
+    int nx = 0, ny = 0, tiles_x = 1, tile_begin = 0, K = -1;
+    long long rowq_bytes = 0;
+    const char* src = nullptr;
+    char* dst = nullptr;
+    InterpW<T> W;
+    T ginv = 0, dt = 0;
+    int eta_s = 0;
+    const T* twp = nullptr;
+    const T* gtab = nullptr;
+
+    for (int t = b < G ? xcd * chunk + (b >> 3) : t_end; t < t_end; t += nb) {
+        const int r = A.tile_real ? uni((int)A.tile_real[t]) : 0;
+        if (r != cur_r) {
+            const RealDesc& Dsc = A.desc[r];
+            nx = uni(Dsc.nx);
+            ny = uni(Dsc.ny);
+            tiles_x = uni(Dsc.wm[A.map].tiles_x);
+            tile_begin = uni(Dsc.wm[A.map].tile_begin);
+            rowq_bytes = (long long)uni(Dsc.pitch) * Q * (long long)sizeof(raw);
+            src = (const char*)uni(Dsc.buf[par]);
+            dst = (char*)uni(Dsc.buf[par ^ 1]);
+            if constexpr (F64) {
+                W.set(uni(Dsc.a[0]), uni(Dsc.a[1]), uni(Dsc.a[2]));
+                ginv = uni(Dsc.inv_tau);
+                dt = uni(Dsc.dt);
+            } else {
+                W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
+                ginv = uni(Dsc.inv_tauf);
+                dt = uni(Dsc.dtf);
+            }
+            eta_s = uni(Dsc.tau_mode);
+            if constexpr (FORCED) {
+                K = uni(Dsc.K);
+                twp = uni((const T*)Dsc.twx);
+                gtab = uni((const T*)Dsc.g[step & 3]);
+            }
+            cur_r = r;
+        }
+        const int local = t - tile_begin;
+        const int tyi = local / tiles_x;
+        const int x0 = (local - tyi * tiles_x) * kTileW;
+        const int y0 = tyi * TH;
+        const int R = min(kTileW - 1, nx - 1 - x0);          // last column lane
+        const int hcol = my_left ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + R + 1 == nx ? 0 : x0 + R + 1);
+        const int hidx = my_left ? 3 : 5 + R;                // LDS index of the halo column
+        const uint32_t colb = col_bytes<raw>(x0 + lx, Q);
+        const uint32_t hcolb = col_bytes<raw>(hcol, Q);
+        auto wrapy = [&](int v) {
+            if (v < 0) v += ny;
+            if (v >= ny) v -= ny;
+            return v >= ny ? v % ny : v;
+        };
+
+        // (b) stage LDS row rr = lattice row y0 - 1 + rr: the populations of
+        // group g (0: c_y < 0, 1: all, 2: c_y > 0) and their halo columns
+        auto stage = [&](int rr, auto gc) {
+            constexpr int g = decltype(gc)::value;
+            const char* rowp = src + (long long)wrapy(y0 - 1 + rr) * rowq_bytes;
+            if (lx <= R) {
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    if constexpr (g == 1 || M::ygroup(q) == g)
+                        sm[M::srow(rr, q) * kLdsW + 4 + lx] =
+                            *(gp<const raw>)(rowp + (long long)q * plane_bytes + colb);
+                });
+            }
+            const bool mine = lx < M::nH() && (g == 1 || (g == 0 ? my_cy < 0 : my_cy > 0));
+            if (mine)
+                sm[(rr * Q + my_slot - (M::nD + M::n0)) * kLdsW + hidx] =
+                    *(gp<const raw>)(rowp + (long long)my_q * plane_bytes + hcolb);
+        };
+        stage(w + 1, std::integral_constant<int, 1>{});
+        if (w == 0) stage(0, std::integral_constant<int, 2>{});
+        if (w == TH - 1) stage(TH + 1, std::integral_constant<int, 0>{});
+        __syncthreads();
+
+        const int y = y0 + w;
+        if (lx <= R && y < ny) {
+            T f[Q];
+            stream_interp<St, SM>(
+                [&](int q, int j, int i) -> T {
+                    return (T)S::ld(&sm[M::srow(w + j, q) * kLdsW + 3 + lx + i]);
+                },
+                W, f);
+            const SiteCtx<T> sctx{ginv, dt, K, gtab, eta_s};
+            T c1 = 0, s1 = 0;
+            if constexpr (FORCED) {
+                if (K >= 0) {
+                    const gp<const T> twx = (gp<const T>)twp;
+                    c1 = twx[2 * (x0 + lx)];
+                    s1 = twx[2 * (x0 + lx) + 1];
+                }
+            }
+            update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), colb,
+                                       A.d_flag);
+        }
+        __syncthreads();                     // before the next tile overwrites LDS
+    }
+
+    if constexpr (FORCED) {
+        const int extra = (int)gridDim.x - G;
+        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+                              extra > 0 ? extra : 8 * nb);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Row-marching form of the same step.  A wavefront owns a strip of 64 columns
 // and marches down a segment of rows [ya, yb).  Populations are loaded once per
 // row, aligned, and kept in a rolling window of registers:
@@ -197,7 +402,9 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
 // lane takes the strip's halo column, fetched for all populations of a row by
 // one gathered load (lane j holds the halo of the j-th population with
 // c_x != 0).  The per-site arithmetic is the same update_site as the tile form,
-// so both forms give bitwise identical results.
+// so both forms give bitwise identical results.  The new populations are
+// written with non-temporal stores: this form serves lattices much larger than
+// the caches, whose new state is not read again until the next launch.
 // ---------------------------------------------------------------------------
 template <class St>
 struct MarchMap {
@@ -430,8 +637,9 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
                 }
             });
             if (active)
-                update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + (long long)y * rowq),
-                                           colb, A.d_flag);
+                update_site<S, St, FORCED, true>(f, sctx, c1, s1, y,
+                                                 (gp<char>)(dst + (long long)y * rowq), colb,
+                                                 A.d_flag);
             // roll the window
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
@@ -710,6 +918,7 @@ static const void* kernel_ptr(int kind) {
     } else {
         if (kind == kKernelMarch) return (const void*)march_kernel<Store, St, SM, FORCED>;
         if (kind == kKernelMarch2) return (const void*)march2_kernel<Store, St, SM, FORCED>;
+        if (kind == kKernelStaged) return (const void*)staged_kernel<Store, St, SM, FORCED>;
         return (const void*)step_kernel<Store, St, SM, FORCED>;
     }
 }

@@ -76,6 +76,7 @@ struct StF64 {
     static constexpr int id = RLBM_F64;
     template <class P> __device__ static T ld(P p) { return *p; }
     template <class P> __device__ static void st(P p, T v) { *p = v; }
+    template <class P> __device__ static void st_nt(P p, T v) { __builtin_nontemporal_store(v, p); }
     __device__ static double to64(raw v) { return v; }
     __device__ static raw from64(double v) { return v; }
 };
@@ -86,6 +87,7 @@ struct StF32 {            // stores F - 1 in FP32: the deviation keeps all 24 bi
     static constexpr int id = RLBM_F32;
     template <class P> __device__ static T ld(P p) { return *p; }
     template <class P> __device__ static void st(P p, T v) { *p = v; }
+    template <class P> __device__ static void st_nt(P p, T v) { __builtin_nontemporal_store(v, p); }
     __device__ static double to64(raw v) { return (double)v; }
     __device__ static raw from64(double v) { return (float)v; }
 };
@@ -96,6 +98,7 @@ struct StF16S {
     static constexpr int id = RLBM_F16S;
     template <class P> __device__ static T ld(P p) { return (float)*p; }
     template <class P> __device__ static void st(P p, T v) { *p = (_Float16)v; }
+    template <class P> __device__ static void st_nt(P p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
     __device__ static double to64(raw v) { return (double)(float)v; }
     __device__ static raw from64(double v) { return (_Float16)(float)v; }
 };
@@ -106,6 +109,9 @@ struct StBF16S {
     static constexpr int id = RLBM_BF16S;
     template <class P> __device__ static T ld(P p) { return __uint_as_float((uint32_t)*p << 16); }
     template <class P> __device__ static void st(P p, T v) { *p = f32_to_bf16_rne(v); }
+    template <class P> __device__ static void st_nt(P p, T v) {
+        __builtin_nontemporal_store(f32_to_bf16_rne(v), p);
+    }
     __device__ static double to64(raw v) { return (double)__uint_as_float((uint32_t)v << 16); }
     __device__ static raw from64(double v) { return f32_to_bf16_rne((float)v); }
 };
@@ -554,8 +560,10 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
     });
 }
 
-// ... storing into global memory: the destination row drow, byte offset own
-template <class S, class St, bool FORCED, class T>
+// ... storing into global memory: the destination row drow, byte offset own.
+// STREAM: non-temporal stores, for lattices far larger than the caches (the
+// new state is not read again before the whole lattice has been swept).
+template <class S, class St, bool FORCED, bool STREAM = false, class T>
 __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
                                             T s1, int y, gp<char> drow, uint32_t own,
                                             int* d_flag) {
@@ -565,7 +573,9 @@ __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T
         f, ctx, c1, s1, y,
         [&](auto qc, T v) {
             constexpr int q = decltype(qc)::value;
-            S::st((gp<raw>)(drow + (long long)q * plane_bytes + own), v);
+            const gp<raw> p = (gp<raw>)(drow + (long long)q * plane_bytes + own);
+            if constexpr (STREAM) S::st_nt(p, v);
+            else S::st(p, v);
         },
         d_flag);
 }

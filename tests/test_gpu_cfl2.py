@@ -84,9 +84,10 @@ def test_cfl2_shear_wave_decays_at_linear_theory_rate():
 
 def test_cfl2_march_form_rejected_and_folded_stencil():
     lat = rl.Lattice(64, 64, 0.7, storage="F32", cfl=1.25)
-    with pytest.raises(rl.RlbmError) as ex:
-        lat.set_kernel("march", 0)
-    assert ex.value.code == rl.EUNSUPPORTED
+    for kind in ("march", "staged"):
+        with pytest.raises(rl.RlbmError) as ex:
+            lat.set_kernel(kind, 0)
+        assert ex.value.code == rl.EUNSUPPORTED
     lat.set_kernel("tile", 2)
     nx, ny = 40, 24
     F0 = workloads.random_populations(SPH.v, ny, nx, seed=5, spread=0.3)

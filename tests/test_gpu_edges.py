@@ -18,11 +18,11 @@ pytestmark = pytest.mark.gpu
 SPH = ostencil.sph26()
 
 
-@pytest.mark.parametrize("kind", ["tile", "march", "march2"])
+@pytest.mark.parametrize("kind", ["tile", "staged", "march", "march2"])
 def test_zero_steps_change_nothing(kind):
     e, bx, by = workloads.noisy_rest(40, 70, 0.01, seed=1)
     lat = rl.Lattice(70, 40, 0.6, storage="F32", forcing=rl.Forcing(1e-4, 2, 4, 1))
-    lat.set_kernel(kind, 2 if kind == "tile" else 0)
+    lat.set_kernel(kind, {"tile": 2, "staged": 4}.get(kind, 0))
     lat.set_state(dev(e), dev(bx), dev(by))
     F0 = host(lat.populations())
     lat.step(0)
@@ -56,9 +56,9 @@ def test_longest_side_one_step(shape):
     nx, ny = shape
     F0 = workloads.random_populations(SPH.v, ny, nx, seed=nx + ny, spread=0.3)
     F1o = orlbm.step(F0, SPH, 0.7, 0.9)
-    for kind in ("tile", "march"):
+    for kind in ("tile", "staged", "march"):
         lat = rl.Lattice(nx, ny, 0.7, storage="F64", cfl=0.9)
-        lat.set_kernel(kind, 2 if kind == "tile" else 0)
+        lat.set_kernel(kind, {"tile": 2, "staged": 4}.get(kind, 0))
         lat.set_populations(dev(oracle_to_lib(F0)))
         lat.step(1)
         err = rel(lib_to_oracle(host(lat.populations())), F1o)

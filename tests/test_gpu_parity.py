@@ -192,7 +192,7 @@ def test_kernel_form_and_shape_do_not_change_results(storage, shape):
     e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=4)
     fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
     ref = None
-    for kind, param in [("tile", 1), ("tile", 2), ("tile", 4), ("tile", 8),
+    for kind, param in [("tile", 1), ("tile", 2), ("tile", 4), ("tile", 8), ("staged", 4),
                         ("march", 0), ("march", 1), ("march", 3), ("march", 16), ("march", 500),
                         ("march2", 0), ("march2", 1), ("march2", 3), ("march2", 16),
                         ("march2", 500)]:
@@ -207,7 +207,7 @@ def test_kernel_form_and_shape_do_not_change_results(storage, shape):
             assert np.array_equal(F, ref), (kind, param)
 
 
-@pytest.mark.parametrize("kind", ["tile", "march", "march2"])
+@pytest.mark.parametrize("kind", ["tile", "staged", "march", "march2"])
 def test_both_kernel_forms_match_oracle(kind):
     """Random populations on a ragged lattice, forced, cfl < 1, both forms."""
     nx, ny = 67, 13
@@ -412,7 +412,7 @@ def test_circ8_parity():
     assert rel(F2, F2o) < 1e-13
 
 
-@pytest.mark.parametrize("kind", ["auto", "march2"])
+@pytest.mark.parametrize("kind", ["auto", "staged", "march2"])
 def test_ensemble_matches_oracle(kind):
     """Independent lattices of different sizes and tau in one persistent
     launch per step (or per pair of steps); realization r draws its force
@@ -422,7 +422,7 @@ def test_ensemble_matches_oracle(kind):
     frs = [rl.Forcing(1e-4, 2.0, 4.0, r) for r in range(4)]
     ens = rl.Ensemble(sizes, taus, storage="F64", forcings=frs)
     if kind != "auto":
-        ens.set_kernel(kind, 5)
+        ens.set_kernel(kind, 4 if kind == "staged" else 5)
     inits = []
     for r, (nx, ny) in enumerate(sizes):
         e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=r)

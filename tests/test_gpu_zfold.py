@@ -102,7 +102,8 @@ def test_fold_kernel_forms_are_bitwise_equal(storage):
     e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=4)
     fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
     ref = None
-    for kind, param in [("tile", 1), ("tile", 4), ("march", 0), ("march", 3), ("march", 500)]:
+    for kind, param in [("tile", 1), ("tile", 4), ("staged", 4), ("march", 0), ("march", 3),
+                        ("march", 500)]:
         lat = rl.Lattice(nx, ny, 0.56, stencil=FOLD, storage=storage, forcing=fr)
         lat.set_kernel(kind, param)
         lat.set_state(dev(e), dev(bx), dev(by))
@@ -114,7 +115,7 @@ def test_fold_kernel_forms_are_bitwise_equal(storage):
             assert np.array_equal(F, ref), (kind, param)
 
 
-@pytest.mark.parametrize("kind", ["tile", "march"])
+@pytest.mark.parametrize("kind", ["tile", "staged", "march"])
 def test_fold_full_size_sampled_one_step(kind):
     """2048 x 2048 forced F32 workload, one step in the benchmark's launch
     configuration, checked at sampled sites against the oracle's stages."""
