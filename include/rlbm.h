@@ -244,8 +244,10 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         param = tile height th in {1, 2, 4, 8} rows of 64 sites.
  *   RLBM_KERNEL_MARCH  -- each wavefront marches down a 64-column strip, loading
  *                         every population row once into a rolling register
- *                         window; param = rows per strip segment (0: chosen
- *                         from the lattice size and the GPU's resident waves).
+ *                         window, and writes with non-temporal stores (this
+ *                         form is for lattices far larger than the caches);
+ *                         param = rows per strip segment (0: chosen from the
+ *                         lattice size and the GPU's resident waves).
  *   RLBM_KERNEL_STAGED -- a block of 4 wavefronts stages the population rows
  *                         of its 64 x 4 tile (its own rows, the needed
  *                         populations of the rows above and below, and the
@@ -257,18 +259,20 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         population is read and written once per two steps;
  *                         param as for RLBM_KERNEL_MARCH.  An odd step count
  *                         ends with one launch of the one-step form.
- * By default the library uses RLBM_KERNEL_MARCH (param 0) for FP32 storage
- * when every resident wavefront gets a segment of at least 8 rows, and
- * RLBM_KERNEL_TILE with th = 4 otherwise; RLBM_KERNEL_MARCH2 is used only
- * when requested (it moves half the bytes per step but, holding two steps'
- * rows in registers, runs fewer wavefronts and was measured slower).  With cfl > 1 only the tile form
- * exists (the marching forms give EUNSUPPORTED).  rlbm_set_tile(th) is
- * rlbm_set_kernel(RLBM_KERNEL_TILE, th).  rlbm_get_kernel reports the form
- * that advances the bulk of the steps.  rlbm_autotune times the tile
- * heights, four segment lengths of the row-marching form (the automatic one
- * and 1/2, 3/2 and 2 times it) and two of the two-step form for `steps`
- * steps each (advancing the state) and keeps the fastest; *h_th receives th,
- * or minus the segment length for a marching form.                         */
+ * By default the library uses RLBM_KERNEL_MARCH (param 0) for FP32, F16S and
+ * BF16S storage when every resident wavefront gets a segment of at least 8
+ * rows, and RLBM_KERNEL_TILE with th = 4 otherwise; RLBM_KERNEL_STAGED and
+ * RLBM_KERNEL_MARCH2 are used only when requested or chosen by the autotuner
+ * (the two-step form moves half the bytes per step but, holding two steps'
+ * rows in registers, runs fewer wavefronts and was measured slower).  With
+ * cfl > 1 only the tile form exists (the other forms give EUNSUPPORTED).
+ * rlbm_set_tile(th) is rlbm_set_kernel(RLBM_KERNEL_TILE, th).
+ * rlbm_get_kernel reports the form that advances the bulk of the steps.
+ * rlbm_autotune times the tile heights, the staged form, four segment lengths
+ * of the row-marching form (the automatic one and 1/2, 3/2 and 2 times it)
+ * and two of the two-step form for `steps` steps each (advancing the state)
+ * and keeps the fastest; *h_th receives th, or minus the segment length for a
+ * marching form.                                                           */
 enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1, RLBM_KERNEL_MARCH2 = 2, RLBM_KERNEL_STAGED = 3 };
 int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param);
 int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param);

@@ -211,19 +211,22 @@ struct Engine {
     }
 
     // Default forms (measured on MI355X): the row-marching kernel when every
-    // wavefront gets a strip segment of at least 8 rows with FP32 storage,
-    // the tile kernel otherwise (small lattices, FP64, 16-bit storage).  The
-    // two-step marching kernel halves the memory traffic but holds both
-    // steps' rows in registers (about 220 VGPRs, 2 wavefronts per SIMD) and
-    // was measured 1.2x (2048^2) to 1.8x (8192^2) slower per step than the
-    // one-step forms, so it is used only when requested.
+    // wavefront gets a strip segment of at least 8 rows (lattices far larger
+    // than the caches) with FP32 or 16-bit storage, the tile kernel otherwise
+    // (small lattices, FP64).  The best segment length depends on how the last
+    // round of segments fills the chip (2048^2 FP32: 160 us at 32 rows, 186 us
+    // at the default 22); rlbm_autotune searches it.  The two-step marching
+    // kernel halves the memory traffic but holds both steps' rows in registers
+    // (about 220 VGPRs, 2 wavefronts per SIMD) and was measured 1.2x (2048^2)
+    // to 1.8x (8192^2) slower per step than the one-step forms, so it is used
+    // only when requested.
     void choose_kind() {
         if (!kind_auto) return;
         Cfg& c = cfg[0];
         c.th = 4;
         const long long waves = (long long)cus * occupancy(kKernelMarch, 4) * 4;
         const bool long_segments = wave_rows(kTileW) >= 8 * std::max(1LL, waves);
-        c.kind = (storage == RLBM_F32 && long_segments && smode != kStreamHalo2) ? kKernelMarch
+        c.kind = (storage != RLBM_F64 && long_segments && smode != kStreamHalo2) ? kKernelMarch
                                                                                 : kKernelTile;
         c.seglen_req = 0;
         pairs = false;
