@@ -62,11 +62,10 @@ __device__ __forceinline__ P* uni(P* p) {
 // ---------------------------------------------------------------------------
 // storage forms.  Registers hold f' = F - shift; memory holds raw(f').
 // ---------------------------------------------------------------------------
+// FP32 -> BF16, round to nearest even: gfx950's v_cvt_pk_bf16_f32 (one
+// instruction; NaN stays NaN).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
 struct StF64 {

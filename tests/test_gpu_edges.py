@@ -123,3 +123,44 @@ def test_one_lattice_ensemble_equals_lattice():
     ens.step(7)
     lat.step(7)
     assert np.array_equal(host(ens.populations(0)), host(lat.populations()))
+
+
+def _bf16_rne(d32):
+    """FP32 -> BF16 bits, round to nearest even (finite inputs)."""
+    u = d32.view(np.uint32).astype(np.uint64)
+    u = u + 0x7FFF + ((u >> 16) & 1)
+    return (u >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("storage", ["F32", "F16S", "BF16S"])
+def test_storage_rounding_is_round_to_nearest_even(storage):
+    """Populations written into the reduced storage forms are rounded to
+    nearest even: the stored deviation F - 1 equals numpy's rounding of the
+    FP32 deviation, bit for bit, including exact ties of both parities."""
+    nx, ny = 64, 8
+    Q = rl.Lattice(nx, ny, 0.7, storage=storage).Q
+    rng = np.random.default_rng(21)
+    F = 1.0 + rng.uniform(-0.3, 0.3, size=(Q, ny, nx))
+    ties = np.array([0x3C008000, 0x3C018000, 0xBC008000, 0xBC018000, 0x3A7F8000,
+                     0x00000000, 0x80000000], dtype=np.uint32).view(np.float32)
+    F.reshape(-1)[:ties.size] = 1.0 + ties.astype(np.float64)
+    h16 = np.array([0x3C00 + 0x0400, 0x1001], dtype=np.uint16).view(np.float16)
+    F.reshape(-1)[ties.size:ties.size + 2] = 1.0 + h16.astype(np.float64) + np.array([2.0 ** -22, -2.0 ** -22])
+    lat = rl.Lattice(nx, ny, 0.7, storage=storage)
+    lat.set_populations(dev(F))
+    got = host(lat.populations())
+    d32 = (F - 1.0).astype(np.float32)
+    if storage == "F32":
+        want = d32.astype(np.float64) + 1.0
+    elif storage == "F16S":
+        want = d32.astype(np.float16).astype(np.float64) + 1.0
+    else:
+        want = (_bf16_rne(d32).astype(np.uint32) << 16).view(np.float32).astype(np.float64) + 1.0
+    assert np.array_equal(got, want)
+    # one step of an unforced lattice keeps every stored value on the storage grid
+    lat.step(1)
+    d = (host(lat.populations()) - 1.0).astype(np.float32)
+    if storage == "F16S":
+        assert np.array_equal(d.astype(np.float16).astype(np.float32), d)
+    elif storage == "BF16S":
+        assert np.all((d.view(np.uint32) & 0xFFFF) == 0)
