@@ -227,8 +227,8 @@ def main():
         a.tune_steps = 0 if a.only else 40
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(a lattice would be split into row slabs, one per GPU); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -50,7 +50,7 @@ extern "C" {
 #define RLBM_EHIP         -3  /* a HIP runtime call failed (see rlbm_last_error) */
 #define RLBM_EUNSTABLE    -4  /* a site became unphysical: eps <= 0, |beta| >= 1,
                                  non-finite, or the Landau solve did not converge */
-#define RLBM_EUNSUPPORTED -5  /* valid request this build does not support */
+#define RLBM_EUNSUPPORTED -5  /* valid request the library does not support */
 
 /* ---- enumerations --------------------------------------------------------- */
 /* Momentum stencil.
