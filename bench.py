@@ -15,10 +15,13 @@ carries the FP64, F16S and BF16S forms of the step (MLUPS, kernel GB/s and
 their field error against the FP64 path after the same steps), the z-folded
 stencil (17 stored populations, exact for the one-layer lattice) in F32 and
 F16S, the same kernels on HBM-resident lattices (2048^2 and 8192^2) and on
-the 256-lattice ensemble, the roofline of the FP32 step kernel (per-launch
+the 256-lattice ensemble, a plain device copy of one 2048^2 step's bytes (the
+practical streaming rate), the roofline of the FP32 step kernel (per-launch
 duration from HIP events around every launch; HBM traffic from the committed
 rocprofv3 counter summary when it matches the kernel sources) and the FP64
-NumPy oracle timed on the host cores for a bounded sample.
+NumPy oracle timed on the host cores for a bounded sample.  Every form is
+timed in the kernel form the library's autotuner picks on a scratch lattice
+of the same configuration.
 Everything except the JSON line goes to stderr.
 """
 import argparse
@@ -178,6 +181,29 @@ def run_ensemble(rl, torch, steps, warmup, chunk=20):
     return out
 
 
+def copy_ceiling(torch, nbytes, reps=20):
+    """Device-to-device copy of nbytes (torch's copy: the runtime's copy
+    kernel), back to back: read + write bytes per second, the practical
+    streaming rate of the machine's HBM for a buffer of that size."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(reps):
+        (b if i % 2 == 0 else a).copy_(a if i % 2 == 0 else b)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": 4 * n, "ms": ms, "gbs": 2 * 4 * n / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(wl, n_steps):
     """The FP64 oracle on the same workload, single thread, a few steps."""
     from threadpoolctl import threadpool_limits
@@ -326,6 +352,10 @@ def main():
                     f"({100 * r['kernel_frac_hbm_peak']:.1f}% of HBM peak)")
 
     if not a.no_extra:
+        # the same bytes as one FP32 step of the 2048^2 lattice (read + write 436 MB)
+        extra["copy_2048_f32_bytes"] = copy_ceiling(torch, 2048 * 2048 * Q * 4)
+        log(f"device copy of 436 MB: {extra['copy_2048_f32_bytes']['gbs']:.0f} GB/s "
+            f"({100 * extra['copy_2048_f32_bytes']['gbs'] / HBM_PEAK_GBS:.1f}% of HBM peak)")
         extra["ensemble256"] = run_ensemble(rl, torch, 200, 20)
         torch.cuda.empty_cache()
         log(f"ensemble256 F32: {extra['ensemble256']['mlups']:.0f} MLUPS, "
