@@ -368,8 +368,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["kernel_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,
-                "kernel": ("rlbm::%s_kernel<StF32, Sph26, unit cfl, forced>"
-                           % ("march" if head["kernel_form"][0] == "march" else "step")),
+                "kernel": ("rlbm::%s<StF32, Sph26, unit cfl, forced>"
+                           % {"tile": "step_kernel", "staged": "staged_kernel",
+                              "march": "march_kernel", "march2": "march2_kernel"}[
+                               head["kernel_form"][0]]),
+                "kernel_form": head["kernel_form"],
                 "algorithmic_bytes_per_launch": per_launch,
                 "kernel_ms": head["kernel_ms"]}
 
