@@ -56,10 +56,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(tag="forced512_F32"):
+def committed_traffic(tag="forced512_F32", kind=None):
     """HBM bytes per launch of the step kernel on a workload, from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on
-    the current kernel sources; else None."""
+    the current kernel sources and (when kind is given) on the same kernel
+    form (tile / staged / march / march2); else None."""
     path = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -68,8 +69,10 @@ def committed_traffic(tag="forced512_F32"):
         f = line.split()
         if len(f) == 2 and f[0] == "kernel_src_sha":
             sha = f[1]
-        elif len(f) == 3 and f[0] == tag and f[1] == "traffic_bytes_per_launch":
-            val = int(f[2])
+        elif len(f) >= 3 and f[0] == tag and f[1] == "traffic_bytes_per_launch":
+            form = f[3].split(":")[0] if len(f) >= 4 else None
+            if kind is None or form is None or form == kind:
+                val = int(f[2])
     if sha != kernel_source_hash():
         return None
     return val
@@ -347,7 +350,7 @@ def main():
                                                       "kernel_gbs", "kernel_frac_hbm_peak",
                                                       "unstable", "kernel_form")}
                 extra[name][key]["traffic_bytes_per_launch"] = committed_traffic(
-                    f"{name}_{storage}" + ("_SPH26_ZFOLD" if fold else ""))
+                    f"{name}_{storage}" + ("_SPH26_ZFOLD" if fold else ""), r["kernel_form"][0])
                 log(f"{name} {key}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
                     f"({100 * r['kernel_frac_hbm_peak']:.1f}% of HBM peak)")
 
@@ -364,7 +367,7 @@ def main():
     head = forms["F32"]
     sites = wl.n * wl.n
     per_launch = 2 * Q * BYTES["F32"] * sites
-    traffic = committed_traffic()
+    traffic = committed_traffic("forced512_F32", head["kernel_form"][0])
     roofline = {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["kernel_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,
