@@ -253,6 +253,10 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         populations of the rows above and below, and the
  *                         halo columns) into LDS with aligned row loads, then
  *                         every site streams from LDS; param = 4 (or 0).
+ *   RLBM_KERNEL_MARCH_PAIRS -- F16S and BF16S storage only: as RLBM_KERNEL_MARCH
+ *                         with every lane on two adjacent columns of a
+ *                         128-column strip, so that each load and store moves
+ *                         a 32-bit pair; param as for RLBM_KERNEL_MARCH.
  *   RLBM_KERNEL_MARCH2 -- two time steps per launch: each wavefront marches
  *                         down a 62-column strip computing the first step
  *                         into registers and the second from them, so every
@@ -269,11 +273,18 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  * rlbm_set_tile(th) is rlbm_set_kernel(RLBM_KERNEL_TILE, th).
  * rlbm_get_kernel reports the form that advances the bulk of the steps.
  * rlbm_autotune times the tile heights, the staged form, four segment lengths
- * of the row-marching form (the automatic one and 1/2, 3/2 and 2 times it)
- * and two of the two-step form for `steps` steps each (advancing the state)
+ * of the row-marching form (the automatic one and 1/2, 3/2 and 2 times it),
+ * the same four of the paired form for 16-bit storage, and two of the
+ * two-step form for `steps` steps each (advancing the state)
  * and keeps the fastest; *h_th receives th, or minus the segment length for a
  * marching form.                                                           */
-enum { RLBM_KERNEL_TILE = 0, RLBM_KERNEL_MARCH = 1, RLBM_KERNEL_MARCH2 = 2, RLBM_KERNEL_STAGED = 3 };
+enum {
+    RLBM_KERNEL_TILE = 0,
+    RLBM_KERNEL_MARCH = 1,
+    RLBM_KERNEL_MARCH2 = 2,
+    RLBM_KERNEL_STAGED = 3,
+    RLBM_KERNEL_MARCH_PAIRS = 4
+};
 int rlbm_set_kernel(rlbm_ctx* ctx, int32_t kind, int32_t param);
 int rlbm_get_kernel(const rlbm_ctx* ctx, int32_t* h_kind, int32_t* h_param);
 int rlbm_set_tile(rlbm_ctx* ctx, int32_t th);

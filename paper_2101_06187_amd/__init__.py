@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
 STENCILS = {"SPH26": 0, "CIRC8": 1, "SPH26_ZFOLD": 2}
 STORAGES = {"F64": 0, "F32": 1, "F16S": 2, "BF16S": 3}
-KERNELS = {"tile": 0, "march": 1, "march2": 2, "staged": 3}
+KERNELS = {"tile": 0, "march": 1, "march2": 2, "staged": 3, "march_pairs": 4}
 _KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 RELAXATION = {"constant": 0, "eta_s": 1}
 
@@ -303,7 +303,8 @@ class Lattice:
 
     def set_kernel(self, kind, param=0):
         """kind "tile" (param = tile height 1/2/4/8), "staged" (param 4),
-        "march" or "march2" (param = rows per strip segment, 0 = automatic)."""
+        "march", "march_pairs" (16-bit storage) or "march2" (param = rows per
+        strip segment, 0 = automatic)."""
         _check(lib().rlbm_set_kernel(self._ctx, KERNELS[kind], int(param)))
 
     def kernel(self):

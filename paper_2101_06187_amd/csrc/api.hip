@@ -242,7 +242,8 @@ struct Engine {
         if (c.kind != kKernelTile) c.th = 4;          // 4 wavefronts per block (kStageTH)
         const int per_cu = occupancy(c.kind, c.th);
         const int slots = cus * per_cu;
-        const int width = c.kind == kKernelMarch2 ? kTileW - 2 : kTileW;
+        const int width = c.kind == kKernelMarch2 ? kTileW - 2
+                          : (c.kind == kKernelMarchPair ? 2 * kTileW : kTileW);
         int seg = c.seglen_req;
         const bool tiled = c.kind == kKernelTile || c.kind == kKernelStaged;
         if (!tiled && seg <= 0) {
@@ -1033,6 +1034,15 @@ int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
         E.cfg[0].kind = kKernelStaged;
         E.cfg[0].th = 4;
         E.pairs = false;
+    } else if (kind == RLBM_KERNEL_MARCH_PAIRS) {
+        if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
+        if (E.smode == kStreamHalo2)
+            return fail(RLBM_EUNSUPPORTED, "the row-marching forms need cfl <= 1");
+        if (E.storage != RLBM_F16S && E.storage != RLBM_BF16S)
+            return fail(RLBM_EUNSUPPORTED, "the paired marching form is for 16-bit storage");
+        E.cfg[0].kind = kKernelMarchPair;
+        E.cfg[0].seglen_req = param;
+        E.pairs = false;
     } else if (kind == RLBM_KERNEL_MARCH || kind == RLBM_KERNEL_MARCH2) {
         if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
         if (E.smode == kStreamHalo2)
@@ -1071,6 +1081,9 @@ int engine_get_kernel(const Engine& E, int32_t* h_kind, int32_t* h_param) {
     } else if (E.cfg[0].kind == kKernelStaged) {
         *h_kind = RLBM_KERNEL_STAGED;
         *h_param = E.cfg[0].th;
+    } else if (E.cfg[0].kind == kKernelMarchPair) {
+        *h_kind = RLBM_KERNEL_MARCH_PAIRS;
+        *h_param = E.cfg[0].seglen;
     } else {
         *h_kind = RLBM_KERNEL_TILE;
         *h_param = E.cfg[0].th;
@@ -1092,16 +1105,20 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     // segment length (0: about one segment per resident wavefront) and with
     // segments 2x (-1), 3/2 x (-2) and 1/2 x (-3) as long; which of these runs
     // fastest depends on how the last round of segments fills the chip
-    const int cand[11][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
+    const int cand[15][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
                              {RLBM_KERNEL_TILE, 4},   {RLBM_KERNEL_TILE, 8},
                              {RLBM_KERNEL_STAGED, 4},
                              {RLBM_KERNEL_MARCH, 0},  {RLBM_KERNEL_MARCH, -1},
                              {RLBM_KERNEL_MARCH, -2}, {RLBM_KERNEL_MARCH, -3},
+                             {RLBM_KERNEL_MARCH_PAIRS, 0},  {RLBM_KERNEL_MARCH_PAIRS, -1},
+                             {RLBM_KERNEL_MARCH_PAIRS, -2}, {RLBM_KERNEL_MARCH_PAIRS, -3},
                              {RLBM_KERNEL_MARCH2, 0}, {RLBM_KERNEL_MARCH2, -1}};
-    int auto_seg[4] = {0, 0, 0, 0};
+    int auto_seg[5] = {0, 0, 0, 0, 0};
+    const bool bits16 = E.storage == RLBM_F16S || E.storage == RLBM_BF16S;
     int rc = RLBM_OK;
     for (const auto& c : cand) {
         if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
+        if (c[0] == RLBM_KERNEL_MARCH_PAIRS && !bits16) continue;
         const int a = auto_seg[c[0]];
         const int param = c[1] >= 0 ? c[1]
                           : std::max(2, c[1] == -1 ? 2 * a : (c[1] == -2 ? (3 * a + 1) / 2 : (a + 1) / 2));
@@ -1129,6 +1146,7 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     if (rc) return rc;
     if (h_th) *h_th = best_kind == RLBM_KERNEL_TILE || best_kind == RLBM_KERNEL_STAGED ? best_param
                                                                                      : -best_param;
+    static_assert(RLBM_KERNEL_MARCH_PAIRS < 5, "auto_seg is indexed by the kernel kind");
     return engine_set_kernel(E, best_kind, best_param);
 }
 

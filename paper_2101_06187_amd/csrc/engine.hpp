@@ -89,7 +89,7 @@ __host__ __device__ inline uint32_t col_bytes(int x, int Q) {
     return (uint32_t)(((x >> 6) * (Q * kTileW) + (x & 63)) * (int)sizeof(Raw));
 }
 
-enum { kKernelTile = 0, kKernelMarch = 1, kKernelMarch2 = 2, kKernelStaged = 3 };
+enum { kKernelTile = 0, kKernelMarch = 1, kKernelMarch2 = 2, kKernelStaged = 3, kKernelMarchPair = 4 };
 
 // Stream modes: general cfl <= 1; cfl == 1 (axis populations move exactly
 // one node); 1 < cfl <= 2 (sources up to two nodes upstream, tile form only).

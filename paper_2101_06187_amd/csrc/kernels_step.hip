@@ -666,6 +666,265 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Paired row-marching form, for the 16-bit storage forms.  As march_kernel,
+// but every lane owns two adjacent columns (2 l, 2 l + 1) of a 128-column
+// strip: each load and store moves one 32-bit pair, so a wavefront's memory
+// instruction carries 256 bytes -- as many as in the FP32 form -- instead of
+// 128.  The window holds the pairs packed.  Horizontal neighbours: the
+// left neighbour of column 2 l is the high half of lane l - 1's pair, the
+// right neighbour of column 2 l + 1 the low half of lane l + 1's pair (one
+// lane exchange serves both columns); the other two are the lane's own
+// halves; the strip's edge columns take the halo columns as in march_kernel.
+// Both sites of a lane go through the same update_site as every other form,
+// so the results are bitwise identical.
+// ---------------------------------------------------------------------------
+template <class S, class St, int SM, bool FORCED>
+__global__ __launch_bounds__(256) void march_pair_kernel(StepArgs A) {
+    static_assert(SM != kStreamHalo2, "the row-marching form streams from the nearest rows only");
+    static_assert(sizeof(typename S::raw) == 2, "pairs of 16-bit populations");
+    constexpr bool UNIT = SM == kStreamUnit;
+    using T = typename S::T;
+    using raw = typename S::raw;
+    using M = MarchMap<St>;
+    constexpr int Q = St::Q;
+    constexpr int NH = M::nH();
+    constexpr int kW = 2 * kTileW;              // columns per strip
+
+    const int64_t step = A.d_step[0] + A.step_off;
+    const int par = (int)((A.d_step[1] + A.launch_off) & 1);
+    const int lane = threadIdx.x;
+    const int wv = uni((int)threadIdx.y);
+
+    const int G = A.tile_blocks;
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int nb = (G - xcd + 7) >> 3;
+    const int n_groups = (A.n_tiles + 3) >> 2;
+    const int chunk = (n_groups + 7) >> 3;
+    const int g_end = min(n_groups, (xcd + 1) * chunk);
+
+    auto half_lo = [](uint32_t u) -> T { return S::from_bits((uint16_t)(u & 0xffffu)); };
+    auto half_hi = [](uint32_t u) -> T { return S::from_bits((uint16_t)(u >> 16)); };
+    auto pair_from = [](uint32_t u, int addr_bytes) -> uint32_t {
+        return (uint32_t)__builtin_amdgcn_ds_bpermute(addr_bytes, (int)u);
+    };
+
+    for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
+        const int u = grp * 4 + wv;
+        if (u >= A.n_tiles) continue;
+        const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
+        const RealDesc& Dsc = A.desc[r];
+        const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
+        const int pitch = uni(Dsc.pitch);
+        const int strips = uni(Dsc.wm[A.map].tiles_x);
+        const int seglen = uni(Dsc.wm[A.map].seglen);
+        const int local = u - uni(Dsc.wm[A.map].tile_begin);
+        const int seg = local / strips;
+        const int strip = local - seg * strips;
+        const int ya = seg * seglen;
+        const int yb = min(ny, ya + seglen);
+        const int x0 = strip * kW;
+        const int Rc = min(kW - 1, nx - 1 - x0);        // last column of the strip
+        const int Lr = Rc >> 1;                         // lane of the last column
+        const bool last_is_b = (Rc & 1) != 0;
+        const int xa = x0 + 2 * lane;                   // this lane's columns xa, xa + 1
+        const bool activeA = 2 * lane <= Rc;
+        const bool activeB = 2 * lane + 1 <= Rc;
+        constexpr long long plane_bytes = kTileW * sizeof(raw);
+        const long long rowq = (long long)pitch * Q * (long long)sizeof(raw);
+        const char* src = (const char*)uni(Dsc.buf[par]);
+        char* dst = (char*)uni(Dsc.buf[par ^ 1]);
+        InterpW<T> W;
+        SiteCtx<T> sctx;
+        W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
+        sctx.ginv = uni(Dsc.inv_tauf);
+        sctx.dt = uni(Dsc.dtf);
+        sctx.K = -1;
+        sctx.eta_s = uni(Dsc.tau_mode);
+        sctx.gtab = nullptr;
+        T c1a = 0, s1a = 0, c1b = 0, s1b = 0;
+        if constexpr (FORCED) {
+            sctx.K = uni(Dsc.K);
+            sctx.gtab = uni((const T*)Dsc.g[step & 3]);
+            if (sctx.K >= 0) {
+                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
+                if (activeA) { c1a = twx[2 * xa]; s1a = twx[2 * xa + 1]; }
+                if (activeB) { c1b = twx[2 * xa + 2]; s1b = twx[2 * xa + 3]; }
+            }
+        }
+        // the pair's byte offset in a row; lanes past the padded row read its last pair
+        const uint32_t colb = col_bytes<raw>(min(xa, pitch - 2), Q);
+        auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
+        auto ld = [&](int q, int yy) -> uint32_t {
+            const char* rowp = src + (long long)wrap(yy) * rowq + (long long)q * plane_bytes;
+            return *(gp<const uint32_t>)(rowp + colb);
+        };
+        int my_q = 0, my_dy = 0;
+        bool my_left = true;
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            if constexpr (M::cx(q) != 0) {
+                if (lane == M::hidx(q)) {
+                    my_q = q;
+                    my_dy = M::cy(q) < 0 ? 1 : 0;
+                    my_left = M::cx(q) > 0;
+                }
+            }
+        });
+        const int hcol = my_left ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + Rc + 1 == nx ? 0 : x0 + Rc + 1);
+        auto gather = [&](int yy) -> uint32_t {       // the halo's 16 bits
+            uint32_t h = 0;
+            if (lane < NH) {
+                const char* p = src + (long long)wrap(yy + my_dy) * rowq +
+                                (long long)my_q * plane_bytes + col_bytes<raw>(hcol, Q);
+                h = *(gp<const uint16_t>)p;
+            }
+            return h;
+        };
+        auto halo_bits = [](uint32_t h, int l) -> uint32_t {
+            return (uint32_t)__builtin_amdgcn_readlane((int)h, l);
+        };
+        // The strip's edge columns take their x-neighbour from the halo.  The
+        // halo enters the lane exchange through the lane that the edge lane
+        // reads -- lane 63's high half for the left halo (lane 0 reads lane 63),
+        // lane Lr + 1's low half for the right halo -- so the permute's result
+        // is used on every lane as it is: a select after the permute lets the
+        // compiler run it under a mask without the edge lane, whose data the
+        // neighbouring lane then does not receive.
+        const int rl = (Lr + 1) & 63;
+        auto left_of = [&](uint32_t v, uint32_t hb) -> T {        // column 2 l - 1
+            const uint32_t s = lane == 63 ? ((v & 0xffffu) | (hb << 16)) : v;
+            return half_hi(pair_from(s, ((lane - 1) & 63) * 4));
+        };
+        auto right_of = [&](uint32_t v, uint32_t hb) -> T {       // column 2 l + 2
+            const uint32_t s = (last_is_b && lane == rl) ? ((v & 0xffff0000u) | hb) : v;
+            return half_lo(pair_from(s, ((lane + 1) & 63) * 4));
+        };
+
+        uint32_t cur[Q], pre[Q], up[M::nU], dn[M::nD];
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            cur[q] = ld(q, ya);
+            if constexpr (M::cy(q) > 0) up[M::uidx(q)] = ld(q, ya - 1);
+            if constexpr (M::cy(q) < 0) dn[M::didx(q)] = ld(q, ya + 1);
+        });
+        uint32_t hp = gather(ya - 1);
+        uint32_t hc = gather(ya);
+        uint32_t hn = 0;
+
+        for (int y = ya; y < yb; ++y) {
+            if (y + 1 < yb) {
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    pre[q] = ld(q, M::cy(q) < 0 ? y + 2 : y + 1);
+                });
+                hn = gather(y + 1);
+            }
+            // (b) stream both columns
+            T fa[Q], fb[Q];
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                constexpr Dir d = St::dir[q];
+                constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+                const uint32_t own = cur[q];
+                uint32_t vert = own;
+                if constexpr (d.cy > 0) vert = up[M::uidx(q)];
+                if constexpr (d.cy < 0) vert = dn[M::didx(q)];
+                const T oa = half_lo(own), ob = half_hi(own);
+                const T va = half_lo(vert), vb = half_hi(vert);
+                if constexpr (d.cx == 0 && d.cy == 0) {
+                    fa[q] = oa;
+                    fb[q] = ob;
+                } else if constexpr (d.cx == 0) {
+                    if constexpr (UNIT && n == 1) {
+                        fa[q] = va;
+                        fb[q] = vb;
+                    } else {
+                        fa[q] = lerp(oa, va, W.a[n - 1]);
+                        fb[q] = lerp(ob, vb, W.a[n - 1]);
+                    }
+                } else {
+                    // x-neighbours upstream of the two columns (c_x > 0: x - 1)
+                    constexpr int H = M::hidx(q);
+                    const uint32_t h_own = halo_bits(d.cy < 0 ? hp : hc, H);   // halo, row y
+                    T na, nb_;
+                    if constexpr (d.cx > 0) {
+                        na = left_of(own, h_own);
+                        nb_ = oa;
+                    } else {
+                        na = (!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_own) : ob;
+                        nb_ = right_of(own, h_own);
+                    }
+                    if constexpr (d.cy == 0) {
+                        if constexpr (UNIT && n == 1) {
+                            fa[q] = na;
+                            fb[q] = nb_;
+                        } else {
+                            fa[q] = lerp(oa, na, W.a[n - 1]);
+                            fb[q] = lerp(ob, nb_, W.a[n - 1]);
+                        }
+                    } else {
+                        const uint32_t h_vert = halo_bits(d.cy > 0 ? hp : hc, H);
+                        T vna, vnb;
+                        if constexpr (d.cx > 0) {
+                            vna = left_of(vert, h_vert);
+                            vnb = va;
+                        } else {
+                            vna = (!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_vert) : vb;
+                            vnb = right_of(vert, h_vert);
+                        }
+                        fa[q] = fma(W.w11[n - 1], vna, fma(W.w10[n - 1], na + va, W.w00[n - 1] * oa));
+                        fb[q] = fma(W.w11[n - 1], vnb, fma(W.w10[n - 1], nb_ + vb, W.w00[n - 1] * ob));
+                    }
+                }
+            });
+            // both sites, then one packed store per population
+            uint16_t outa[Q], outb[Q];
+            if (activeA)
+                update_site_to<S, St, FORCED>(
+                    fa, sctx, c1a, s1a, y,
+                    [&](auto qc, raw r) { outa[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
+                    A.d_flag);
+            if (activeB)
+                update_site_to<S, St, FORCED>(
+                    fb, sctx, c1b, s1b, y,
+                    [&](auto qc, raw r) { outb[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
+                    A.d_flag);
+            if (activeA) {
+                const gp<char> drow = (gp<char>)(dst + (long long)y * rowq);
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    const uint32_t ba = outa[q], bb = outb[q];   // values, not a select of addresses
+                    const uint32_t pk = ba | ((activeB ? bb : ba) << 16);
+                    __builtin_nontemporal_store(pk, (gp<uint32_t>)(drow + (long long)q * plane_bytes + colb));
+                });
+            }
+            // roll the window
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                if constexpr (M::cy(q) > 0) {
+                    up[M::uidx(q)] = cur[q];
+                    cur[q] = pre[q];
+                } else if constexpr (M::cy(q) < 0) {
+                    cur[q] = dn[M::didx(q)];
+                    dn[M::didx(q)] = pre[q];
+                } else {
+                    cur[q] = pre[q];
+                }
+            });
+            hp = hc;
+            hc = hn;
+        }
+    }
+
+    if constexpr (FORCED) {
+        const int extra = (int)gridDim.x - G;
+        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+                              extra > 0 ? extra : 8 * nb);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Two steps per launch, row-marching.  A wavefront owns a strip of 62 output
 // columns [x0, x0 + 62) and marches down its segment of rows [ya, yb) as in
 // march_kernel, with 64 lanes on the columns x0 - 1 .. x0 + 62:
@@ -853,11 +1112,8 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             T fn[Q];
             update_site_to<S, St, FORCED>(
                 f, c0, cs, sn, wrap(rr),
-                [&](auto qc, T v) {
-                    constexpr int q = decltype(qc)::value;
-                    raw t;
-                    S::st(&t, v);                  // the value a one-step launch stores
-                    fn[q] = (T)S::ld(&t);
+                [&](auto qc, raw r) {              // the value a one-step launch stores
+                    fn[decltype(qc)::value] = (T)S::ld(&r);
                 },
                 A.d_flag);
             // step s + 1 at row rr - 1 from step-s rows rr - 2, rr - 1, rr
@@ -919,6 +1175,12 @@ static const void* kernel_ptr(int kind) {
         if (kind == kKernelMarch) return (const void*)march_kernel<Store, St, SM, FORCED>;
         if (kind == kKernelMarch2) return (const void*)march2_kernel<Store, St, SM, FORCED>;
         if (kind == kKernelStaged) return (const void*)staged_kernel<Store, St, SM, FORCED>;
+        if (kind == kKernelMarchPair) {
+            if constexpr (sizeof(typename Store::raw) == 2)
+                return (const void*)march_pair_kernel<Store, St, SM, FORCED>;
+            else
+                return nullptr;
+        }
         return (const void*)step_kernel<Store, St, SM, FORCED>;
     }
 }

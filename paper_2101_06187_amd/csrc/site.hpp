@@ -76,6 +76,7 @@ struct StF64 {
     template <class P> __device__ static T ld(P p) { return *p; }
     template <class P> __device__ static void st(P p, T v) { *p = v; }
     template <class P> __device__ static void st_nt(P p, T v) { __builtin_nontemporal_store(v, p); }
+    __device__ static raw fma_round(T a, T b, T c) { return fma(a, b, c); }
     __device__ static double to64(raw v) { return v; }
     __device__ static raw from64(double v) { return v; }
 };
@@ -87,6 +88,7 @@ struct StF32 {            // stores F - 1 in FP32: the deviation keeps all 24 bi
     template <class P> __device__ static T ld(P p) { return *p; }
     template <class P> __device__ static void st(P p, T v) { *p = v; }
     template <class P> __device__ static void st_nt(P p, T v) { __builtin_nontemporal_store(v, p); }
+    __device__ static raw fma_round(T a, T b, T c) { return fmaf(a, b, c); }
     __device__ static double to64(raw v) { return (double)v; }
     __device__ static raw from64(double v) { return (float)v; }
 };
@@ -97,7 +99,18 @@ struct StF16S {
     static constexpr int id = RLBM_F16S;
     template <class P> __device__ static T ld(P p) { return (float)*p; }
     template <class P> __device__ static void st(P p, T v) { *p = (_Float16)v; }
+    __device__ static T from_bits(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
     template <class P> __device__ static void st_nt(P p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
+    // a * b + c rounded once, from its exact value, to FP16 (round to nearest
+    // even): v_fma_mixlo_f16 with three FP32 operands.  Written out so that
+    // every kernel form rounds the same way: left to itself the compiler fuses
+    // the FP32 multiply-add and the conversion in some kernels and rounds
+    // twice (FP32, then FP16, packing two results) in others.
+    __device__ static raw fma_round(T a, T b, T c) {
+        uint32_t r;   // the instruction writes the low half
+        asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+        return __builtin_bit_cast(_Float16, (uint16_t)r);
+    }
     __device__ static double to64(raw v) { return (double)(float)v; }
     __device__ static raw from64(double v) { return (_Float16)(float)v; }
 };
@@ -108,6 +121,9 @@ struct StBF16S {
     static constexpr int id = RLBM_BF16S;
     template <class P> __device__ static T ld(P p) { return __uint_as_float((uint32_t)*p << 16); }
     template <class P> __device__ static void st(P p, T v) { *p = f32_to_bf16_rne(v); }
+    __device__ static T from_bits(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+    // the FP32 multiply-add, rounded to nearest even BF16
+    __device__ static raw fma_round(T a, T b, T c) { return f32_to_bf16_rne(fmaf(a, b, c)); }
     template <class P> __device__ static void st_nt(P p, T v) {
         __builtin_nontemporal_store(f32_to_bf16_rne(v), p);
     }
@@ -392,8 +408,9 @@ struct SiteCtx {
     int eta_s;             // 1: relaxation time tau(eps) = tau eps^(-1/4) (constant eta/s)
 };
 
-// sink(qc, v) receives population qc (a std::integral_constant) of the new
-// state, v = F_q - shift in the compute type.
+// sink(qc, r) receives population qc (a std::integral_constant) of the new
+// state as the storage value r = raw(F_q - shift): the collision's last
+// multiply-add, rounded to the storage type by S::fma_round.
 template <class S, class St, bool FORCED, class T, class Sink>
 __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
                                                T s1, int y, Sink&& sink, int* d_flag) {
@@ -536,7 +553,7 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
             // v = (0, 0, +-1): t = 0, no odd part, rate omega = g
             sfor<0, Cl.nplus>([&](auto i) {
                 constexpr int q = Cl.first + decltype(i)::value;
-                sink(std::integral_constant<int, q>{}, fma(omg, f[q], e0));
+                sink(std::integral_constant<int, q>{}, S::fma_round(omg, f[q], e0));
             });
         } else {
             const T ep = fma((T)(m * m), SN[di], e0);
@@ -545,14 +562,14 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
             const T mp = fma(gm[mi], tn[di], omg);
             sfor<0, Cl.nplus>([&](auto i) {
                 constexpr int q = Cl.first + decltype(i)::value;
-                sink(std::integral_constant<int, q>{}, fma(mp, f[q], Kp));
+                sink(std::integral_constant<int, q>{}, S::fma_round(mp, f[q], Kp));
             });
             if constexpr (Cl.nminus > 0) {
                 const T Km = ep - op;
                 const T mm = fma(-gm[mi], tn[di], omg);
                 sfor<0, Cl.nminus>([&](auto i) {
                     constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
-                    sink(std::integral_constant<int, q>{}, fma(mm, f[q], Km));
+                    sink(std::integral_constant<int, q>{}, S::fma_round(mm, f[q], Km));
                 });
             }
         }
@@ -570,11 +587,11 @@ __device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T
     constexpr long long plane_bytes = kTileW * sizeof(raw);
     update_site_to<S, St, FORCED>(
         f, ctx, c1, s1, y,
-        [&](auto qc, T v) {
+        [&](auto qc, raw r) {
             constexpr int q = decltype(qc)::value;
             const gp<raw> p = (gp<raw>)(drow + (long long)q * plane_bytes + own);
-            if constexpr (STREAM) S::st_nt(p, v);
-            else S::st(p, v);
+            if constexpr (STREAM) __builtin_nontemporal_store(r, p);
+            else *p = r;
         },
         d_flag);
 }

@@ -437,3 +437,59 @@ def test_ensemble_matches_oracle(kind):
         say("ensemble", r, rel(got, F))
         assert rel(got, F) < 1e-13
     assert ens.check() == rl.OK
+
+
+@pytest.mark.parametrize("storage", ["F16S", "BF16S"])
+@pytest.mark.parametrize("shape,cfl,forced", [((96, 104), 1.0, True), ((130, 37), 1.0, True),
+                                              ((37, 9), 0.9, True), ((200, 66), 0.9, False),
+                                              ((256, 20), 1.0, True)])
+def test_paired_form_is_bitwise_equal_to_tile_form(storage, shape, cfl, forced):
+    """The paired marching form (two columns per lane, 128-column strips) on
+    ragged lattices -- the last strip 2, 37, 72 or 128 columns wide, one or
+    both columns of the last lane active, a single short strip -- equals the
+    tile form bit for bit over 5 steps, for several segment lengths."""
+    nx, ny = shape
+    e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=nx + ny)
+    # the driven shell 2 <= |k| <= 5, narrowed to stay below the Nyquist wave
+    # number of the 9-row lattice
+    fr = rl.Forcing(1e-4, 2.0, min(5.0, min(nx, ny) // 2 - 1), 3) if forced else None
+
+    def run(kind, param):
+        lat = rl.Lattice(nx, ny, 0.56, storage=storage, cfl=cfl, forcing=fr)
+        lat.set_kernel(kind, param)
+        lat.set_state(dev(e), dev(bx), dev(by))
+        lat.step(5)
+        assert lat.kernel() == (kind, param) or param == 0
+        assert lat.check() == rl.OK
+        return host(lat.populations())
+
+    ref = run("tile", 4)
+    for param in (0, 1, 3, 16, 500):
+        assert np.array_equal(run("march_pairs", param), ref), param
+
+
+def test_paired_form_rejected_for_32_and_64_bit_storage():
+    for storage in ("F64", "F32"):
+        lat = rl.Lattice(64, 64, 0.7, storage=storage)
+        with pytest.raises(rl.RlbmError) as ex:
+            lat.set_kernel("march_pairs", 0)
+        assert ex.value.code == rl.EUNSUPPORTED
+
+
+def test_paired_form_in_an_ensemble():
+    """16-bit ensemble of uneven lattices in the paired form equals the tile form."""
+    sizes = [(64, 64), (130, 64), (64, 128), (96, 40)]
+    taus = [0.55, 0.7, 0.61, 0.8]
+    frs = [rl.Forcing(1e-4, 2.0, 4.0, r) for r in range(4)]
+    out = []
+    for kind, param in (("tile", 4), ("march_pairs", 5)):
+        ens = rl.Ensemble(sizes, taus, storage="F16S", forcings=frs)
+        ens.set_kernel(kind, param)
+        for r, (nx, ny) in enumerate(sizes):
+            e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=r)
+            ens.set_state(r, dev(e), dev(bx), dev(by))
+        ens.step(3)
+        out.append([host(ens.populations(r)) for r in range(len(sizes))])
+        assert ens.check() == rl.OK
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
