@@ -241,7 +241,7 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=None,
                     help="steps per candidate of the library's autotuner, run on a scratch "
                          "lattice before each form is timed (scaled down as 512/n on the "
-                         "larger lattices, at least 4; 0: the library's default form). "
+                         "larger lattices, at least 16; 0: the library's default form). "
                          "Default 40, and 0 with --only")
     ap.add_argument("--form", default=None, metavar="KIND:PARAM",
                     help="with --only: time this kernel form (e.g. march:22 or tile:4)")
@@ -286,7 +286,7 @@ def main():
         tune = a.tune_steps or 0
         lat, r = run_form(rl, torch, w, storage, a.steps, a.warmup, 50, min(a.steps, 200),
                           st[0] if st else "SPH26",
-                          tune_steps=max(4, tune * 512 // w.n) if tune else 0, form=form)
+                          tune_steps=max(16, tune * 512 // w.n) if tune else 0, form=form)
         r["unstable"] = lat.check() != rl.OK
         log(f"{name} {storage}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms'] * 1e3:.2f} us "
             f"= {r['kernel_gbs']:.0f} GB/s")
@@ -340,7 +340,7 @@ def main():
                 storage, _, fold = key.partition("_")
                 lat, r = run_form(rl, torch, w, storage, steps, 20, 20, 20,
                                   "SPH26_ZFOLD" if fold else "SPH26",
-                                  tune_steps=max(4, a.tune_steps * 512 // w.n)
+                                  tune_steps=max(16, a.tune_steps * 512 // w.n)
                                   if a.tune_steps else 0)
                 r["unstable"] = lat.check() != rl.OK
                 lat.close()

@@ -272,12 +272,12 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  * cfl > 1 only the tile form exists (the other forms give EUNSUPPORTED).
  * rlbm_set_tile(th) is rlbm_set_kernel(RLBM_KERNEL_TILE, th).
  * rlbm_get_kernel reports the form that advances the bulk of the steps.
- * rlbm_autotune times the tile heights, the staged form, four segment lengths
- * of the row-marching form (the automatic one and 1/2, 3/2 and 2 times it),
- * the same four of the paired form for 16-bit storage, and two of the
- * two-step form for `steps` steps each (advancing the state)
- * and keeps the fastest; *h_th receives th, or minus the segment length for a
- * marching form.                                                           */
+ * rlbm_autotune times the tile heights, the staged form, five segment lengths
+ * of the row-marching form (the automatic one and 1/2, 3/4, 3/2 and 2 times
+ * it; a length two of them share is timed once), the same five of the paired
+ * form for 16-bit storage, and two of the two-step form for `steps` steps
+ * each (advancing the state) and keeps the fastest; *h_th receives th, or
+ * minus the segment length for a marching form.                            */
 enum {
     RLBM_KERNEL_TILE = 0,
     RLBM_KERNEL_MARCH = 1,

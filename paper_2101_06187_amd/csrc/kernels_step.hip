@@ -677,9 +677,16 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
 // halves; the strip's edge columns take the halo columns as in march_kernel.
 // Both sites of a lane go through the same update_site as every other form,
 // so the results are bitwise identical.
+// The lane computes column A, then column B, so one site's streamed
+// populations are live at a time, and asks for three wavefronts per SIMD
+// (at most 168 VGPRs; the forced 26-velocity kernel spills a few values):
+// a 16-bit lattice larger than the caches is bound by the bytes in flight,
+// and this form keeps 26 x 256 bytes in flight per wavefront (measured at
+// 8192^2 F16S: 1.91 ms per step, 2.08 ms with two wavefronts per SIMD,
+// 2.09 ms for the one-column form).
 // ---------------------------------------------------------------------------
 template <class S, class St, int SM, bool FORCED>
-__global__ __launch_bounds__(256) void march_pair_kernel(StepArgs A) {
+__global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
     static_assert(SM != kStreamHalo2, "the row-marching form streams from the nearest rows only");
     static_assert(sizeof(typename S::raw) == 2, "pairs of 16-bit populations");
     constexpr bool UNIT = SM == kStreamUnit;
@@ -820,8 +827,11 @@ __global__ __launch_bounds__(256) void march_pair_kernel(StepArgs A) {
                 });
                 hn = gather(y + 1);
             }
-            // (b) stream both columns
-            T fa[Q], fb[Q];
+            // (b)-(e) column A, then column B: one site's streamed populations
+            // are live at a time.  The lane exchanges run on every lane (the
+            // permutes sit outside the activity branches).
+            T f[Q];
+            uint32_t outp[Q];                     // the new pairs: A low, B high
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
                 constexpr Dir d = St::dir[q];
@@ -830,72 +840,90 @@ __global__ __launch_bounds__(256) void march_pair_kernel(StepArgs A) {
                 uint32_t vert = own;
                 if constexpr (d.cy > 0) vert = up[M::uidx(q)];
                 if constexpr (d.cy < 0) vert = dn[M::didx(q)];
-                const T oa = half_lo(own), ob = half_hi(own);
-                const T va = half_lo(vert), vb = half_hi(vert);
+                const T oa = half_lo(own), va = half_lo(vert);
                 if constexpr (d.cx == 0 && d.cy == 0) {
-                    fa[q] = oa;
-                    fb[q] = ob;
+                    f[q] = oa;
                 } else if constexpr (d.cx == 0) {
-                    if constexpr (UNIT && n == 1) {
-                        fa[q] = va;
-                        fb[q] = vb;
-                    } else {
-                        fa[q] = lerp(oa, va, W.a[n - 1]);
-                        fb[q] = lerp(ob, vb, W.a[n - 1]);
-                    }
+                    if constexpr (UNIT && n == 1) f[q] = va;
+                    else f[q] = lerp(oa, va, W.a[n - 1]);
                 } else {
-                    // x-neighbours upstream of the two columns (c_x > 0: x - 1)
+                    // x-neighbour upstream of column A: 2 l - 1 (c_x > 0) or 2 l + 1
                     constexpr int H = M::hidx(q);
                     const uint32_t h_own = halo_bits(d.cy < 0 ? hp : hc, H);   // halo, row y
-                    T na, nb_;
-                    if constexpr (d.cx > 0) {
-                        na = left_of(own, h_own);
-                        nb_ = oa;
-                    } else {
-                        na = (!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_own) : ob;
-                        nb_ = right_of(own, h_own);
-                    }
+                    const T na = d.cx > 0 ? left_of(own, h_own)
+                                          : ((!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_own)
+                                                                        : half_hi(own));
                     if constexpr (d.cy == 0) {
-                        if constexpr (UNIT && n == 1) {
-                            fa[q] = na;
-                            fb[q] = nb_;
-                        } else {
-                            fa[q] = lerp(oa, na, W.a[n - 1]);
-                            fb[q] = lerp(ob, nb_, W.a[n - 1]);
-                        }
+                        if constexpr (UNIT && n == 1) f[q] = na;
+                        else f[q] = lerp(oa, na, W.a[n - 1]);
                     } else {
                         const uint32_t h_vert = halo_bits(d.cy > 0 ? hp : hc, H);
-                        T vna, vnb;
-                        if constexpr (d.cx > 0) {
-                            vna = left_of(vert, h_vert);
-                            vnb = va;
-                        } else {
-                            vna = (!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_vert) : vb;
-                            vnb = right_of(vert, h_vert);
-                        }
-                        fa[q] = fma(W.w11[n - 1], vna, fma(W.w10[n - 1], na + va, W.w00[n - 1] * oa));
-                        fb[q] = fma(W.w11[n - 1], vnb, fma(W.w10[n - 1], nb_ + vb, W.w00[n - 1] * ob));
+                        const T vna = d.cx > 0 ? left_of(vert, h_vert)
+                                               : ((!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_vert)
+                                                                             : half_hi(vert));
+                        f[q] = fma(W.w11[n - 1], vna, fma(W.w10[n - 1], na + va, W.w00[n - 1] * oa));
                     }
                 }
             });
-            // both sites, then one packed store per population
-            uint16_t outa[Q], outb[Q];
             if (activeA)
                 update_site_to<S, St, FORCED>(
-                    fa, sctx, c1a, s1a, y,
-                    [&](auto qc, raw r) { outa[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
+                    f, sctx, c1a, s1a, y,
+                    [&](auto qc, raw r) { outp[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
                     A.d_flag);
+            // column B converts the window's halves anew: values kept from column
+            // A's pass would stay live through A's update and cost registers
+#pragma unroll
+            for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(cur[i]));
+#pragma unroll
+            for (int i = 0; i < M::nU; ++i) asm volatile("" : "+v"(up[i]));
+#pragma unroll
+            for (int i = 0; i < M::nD; ++i) asm volatile("" : "+v"(dn[i]));
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                constexpr Dir d = St::dir[q];
+                constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+                const uint32_t own = cur[q];
+                uint32_t vert = own;
+                if constexpr (d.cy > 0) vert = up[M::uidx(q)];
+                if constexpr (d.cy < 0) vert = dn[M::didx(q)];
+                const T ob = half_hi(own), vb = half_hi(vert);
+                if constexpr (d.cx == 0 && d.cy == 0) {
+                    f[q] = ob;
+                } else if constexpr (d.cx == 0) {
+                    if constexpr (UNIT && n == 1) f[q] = vb;
+                    else f[q] = lerp(ob, vb, W.a[n - 1]);
+                } else {
+                    // x-neighbour upstream of column B: 2 l (c_x > 0) or 2 l + 2
+                    constexpr int H = M::hidx(q);
+                    T nb;
+                    if constexpr (d.cx > 0) nb = half_lo(own);
+                    else nb = right_of(own, halo_bits(d.cy < 0 ? hp : hc, H));
+                    if constexpr (d.cy == 0) {
+                        if constexpr (UNIT && n == 1) f[q] = nb;
+                        else f[q] = lerp(ob, nb, W.a[n - 1]);
+                    } else {
+                        T vnb;
+                        if constexpr (d.cx > 0) vnb = half_lo(vert);
+                        else vnb = right_of(vert, halo_bits(d.cy > 0 ? hp : hc, H));
+                        f[q] = fma(W.w11[n - 1], vnb, fma(W.w10[n - 1], nb + vb, W.w00[n - 1] * ob));
+                    }
+                }
+            });
             if (activeB)
                 update_site_to<S, St, FORCED>(
-                    fb, sctx, c1b, s1b, y,
-                    [&](auto qc, raw r) { outb[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
+                    f, sctx, c1b, s1b, y,
+                    [&](auto qc, raw r) {
+                        constexpr int q = decltype(qc)::value;
+                        outp[q] = (outp[q] & 0xffffu) | ((uint32_t)__builtin_bit_cast(uint16_t, r) << 16);
+                    },
                     A.d_flag);
+            // one packed store per population; a lane whose column B lies past the
+            // lattice writes +0 into that padding column
             if (activeA) {
                 const gp<char> drow = (gp<char>)(dst + (long long)y * rowq);
                 sfor<0, Q>([&](auto iq) {
                     constexpr int q = decltype(iq)::value;
-                    const uint32_t ba = outa[q], bb = outb[q];   // values, not a select of addresses
-                    const uint32_t pk = ba | ((activeB ? bb : ba) << 16);
+                    const uint32_t pk = activeB ? outp[q] : (outp[q] & 0xffffu);
                     __builtin_nontemporal_store(pk, (gp<uint32_t>)(drow + (long long)q * plane_bytes + colb));
                 });
             }
