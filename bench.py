@@ -21,7 +21,10 @@ duration from HIP events around every launch; HBM traffic from the committed
 rocprofv3 counter summary when it matches the kernel sources) and the FP64
 NumPy oracle timed on the host cores for a bounded sample.  Every form is
 timed in the kernel form the library's autotuner picks on a scratch lattice
-of the same configuration.
+of the same configuration.  Kernel GB/s are algorithmic bytes (2 Q s per site
+and step) per launch over the launch's duration; a two-step launch counts both
+steps' bytes and moves about half of them through HBM (the committed traffic
+counters show it).
 Everything except the JSON line goes to stderr.
 """
 import argparse
@@ -39,6 +42,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 Q = 26
 BYTES = {"F64": 8, "F32": 4, "F16S": 2, "BF16S": 2}
+STEPS_PER_LAUNCH = {"march2": 2}         # kernel forms that advance more than one step per launch
 METRIC = "MLUPS + HBM GB/s (% peak): FP32/FP16-storage vs FP64 step at stated field error"
 
 
@@ -132,7 +136,10 @@ def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH2
     if form is not None:
         lat.set_kernel(*form)
     ms = time_steps(lat, torch, steps, warmup, chunk)
-    kms = lat.profile_step_kernel(prof_n)
+    kind = lat.kernel()
+    spl = STEPS_PER_LAUNCH.get(kind[0], 1)          # the two-step form advances 2 per launch
+    n_prof = max(1, prof_n // spl)                  # the same number of steps for every form
+    kms = lat.profile_step_kernel(n_prof)
     sites = wl.n * wl.n
     algo = 2 * lat.Q * BYTES[storage] * sites
     out = {
@@ -141,12 +148,13 @@ def run_form(rl, torch, wl, storage, steps, warmup, chunk, prof_n, stencil="SPH2
         "ms_per_step": ms,
         "mlups": sites / (ms * 1e-3) / 1e6,
         "kernel_ms": kms,
-        "kernel_gbs": algo / (kms * 1e-3) / 1e9,
+        "steps_per_launch": spl,
+        "kernel_gbs": spl * algo / (kms * 1e-3) / 1e9,
         "step_gbs": algo / (ms * 1e-3) / 1e9,
-        "steps_done": warmup + steps + prof_n,
+        "steps_done": warmup + steps + n_prof * spl,
     }
     out["kernel_frac_hbm_peak"] = out["kernel_gbs"] / HBM_PEAK_GBS
-    out["kernel_form"] = list(lat.kernel())
+    out["kernel_form"] = list(kind)
     out["autotuned"] = tuned
     return lat, out
 
@@ -347,8 +355,9 @@ def main():
                 del lat
                 torch.cuda.empty_cache()
                 extra[name][key] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms",
-                                                      "kernel_gbs", "kernel_frac_hbm_peak",
-                                                      "unstable", "kernel_form")}
+                                                      "steps_per_launch", "kernel_gbs",
+                                                      "kernel_frac_hbm_peak", "unstable",
+                                                      "kernel_form")}
                 extra[name][key]["traffic_bytes_per_launch"] = committed_traffic(
                     f"{name}_{storage}" + ("_SPH26_ZFOLD" if fold else ""), r["kernel_form"][0])
                 log(f"{name} {key}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s "
@@ -366,14 +375,15 @@ def main():
 
     head = forms["F32"]
     sites = wl.n * wl.n
-    per_launch = 2 * Q * BYTES["F32"] * sites
+    per_launch = head["steps_per_launch"] * 2 * Q * BYTES["F32"] * sites
     traffic = committed_traffic("forced512_F32", head["kernel_form"][0])
     roofline = {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["kernel_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,
                 "kernel": ("rlbm::%s<StF32, Sph26, unit cfl, forced>"
                            % {"tile": "step_kernel", "staged": "staged_kernel",
-                              "march": "march_kernel", "march2": "march2_kernel"}[
+                              "march": "march_kernel", "march2": "march2_kernel",
+                              "march_pairs": "march_pair_kernel"}[
                                head["kernel_form"][0]]),
                 "kernel_form": head["kernel_form"],
                 "algorithmic_bytes_per_launch": per_launch,

@@ -261,23 +261,27 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         down a 62-column strip computing the first step
  *                         into registers and the second from them, so every
  *                         population is read and written once per two steps;
- *                         param as for RLBM_KERNEL_MARCH.  An odd step count
- *                         ends with one launch of the one-step form.
+ *                         param = rows per strip segment, 0 = 12 rows.  An
+ *                         odd step count ends with one launch of the
+ *                         one-step form.
  * By default the library uses RLBM_KERNEL_MARCH (param 0) for FP32, F16S and
  * BF16S storage when every resident wavefront gets a segment of at least 8
  * rows, and RLBM_KERNEL_TILE with th = 4 otherwise; RLBM_KERNEL_STAGED and
  * RLBM_KERNEL_MARCH2 are used only when requested or chosen by the autotuner
  * (the two-step form moves half the bytes per step but, holding two steps'
- * rows in registers, runs fewer wavefronts and was measured slower).  With
+ * rows in registers, runs fewer wavefronts: with short segments, param 0 =
+ * 12 rows, it is faster than the one-step form for FP32 lattices much larger
+ * than the caches, slower elsewhere).  With
  * cfl > 1 only the tile form exists (the other forms give EUNSUPPORTED).
  * rlbm_set_tile(th) is rlbm_set_kernel(RLBM_KERNEL_TILE, th).
  * rlbm_get_kernel reports the form that advances the bulk of the steps.
  * rlbm_autotune times the tile heights, the staged form, five segment lengths
  * of the row-marching form (the automatic one and 1/2, 3/4, 3/2 and 2 times
  * it; a length two of them share is timed once), the same five of the paired
- * form for 16-bit storage, and two of the two-step form for `steps` steps
- * each (advancing the state) and keeps the fastest; *h_th receives th, or
- * minus the segment length for a marching form.                            */
+ * form for 16-bit storage, and the two-step form with segments of 8, 12,
+ * 16, 24 and 32 rows, for `steps` steps each (advancing the state) and keeps
+ * the fastest; *h_th receives th, or minus the segment length for a
+ * marching form.                                                           */
 enum {
     RLBM_KERNEL_TILE = 0,
     RLBM_KERNEL_MARCH = 1,

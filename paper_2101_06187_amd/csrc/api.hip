@@ -217,9 +217,11 @@ struct Engine {
     // round of segments fills the chip (2048^2 FP32: 160 us at 32 rows, 186 us
     // at the default 22); rlbm_autotune searches it.  The two-step marching
     // kernel halves the memory traffic but holds both steps' rows in registers
-    // (about 220 VGPRs, 2 wavefronts per SIMD) and was measured 1.2x (2048^2)
-    // to 1.8x (8192^2) slower per step than the one-step forms, so it is used
-    // only when requested.
+    // (about 210 VGPRs, 2 wavefronts per SIMD); with short segments it is
+    // 6-10 % faster per step than the one-step form for FP32 lattices far
+    // larger than the caches and slower for 16-bit storage, the folded stencil
+    // and cache-resident lattices.  It is used when requested or chosen by
+    // rlbm_autotune.
     void choose_kind() {
         if (!kind_auto) return;
         Cfg& c = cfg[0];
@@ -246,7 +248,13 @@ struct Engine {
                           : (c.kind == kKernelMarchPair ? 2 * kTileW : kTileW);
         int seg = c.seglen_req;
         const bool tiled = c.kind == kKernelTile || c.kind == kKernelStaged;
-        if (!tiled && seg <= 0) {
+        if (c.kind == kKernelMarch2 && seg <= 0) {
+            // two-step form: short segments (measured, FP32: 2048^2 best at 12
+            // rows, 153 us per step; 8192^2 at 16-32 rows; the one-segment-per-
+            // wavefront length of the one-step forms, 35 and 547 rows, runs
+            // 1.5-2x slower)
+            seg = 12;
+        } else if (!tiled && seg <= 0) {
             // about one strip segment per resident wavefront, at least 2 rows,
             // and no more segments than resident wavefronts (a few too many
             // would take a second round of the whole grid)
@@ -1105,8 +1113,9 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     // segment length (0: about one segment per resident wavefront) and with
     // segments 2x (-1), 3/2 x (-2), 1/2 x (-3) and 3/4 x (-4) as long; which
     // of these runs fastest depends on how the rounds of segments fill the
-    // chip (measured: 16-bit storage at 2048^2, 105 us at 8 rows, 127 us at 11)
-    const int cand[17][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
+    // chip (measured: 16-bit storage at 2048^2, 105 us at 8 rows, 127 us at 11);
+    // the two-step form with segments of 12 (its default), 8, 16, 24, 32 rows
+    const int cand[20][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
                              {RLBM_KERNEL_TILE, 4},   {RLBM_KERNEL_TILE, 8},
                              {RLBM_KERNEL_STAGED, 4},
                              {RLBM_KERNEL_MARCH, 0},  {RLBM_KERNEL_MARCH, -1},
@@ -1115,9 +1124,11 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
                              {RLBM_KERNEL_MARCH_PAIRS, 0},  {RLBM_KERNEL_MARCH_PAIRS, -1},
                              {RLBM_KERNEL_MARCH_PAIRS, -2}, {RLBM_KERNEL_MARCH_PAIRS, -3},
                              {RLBM_KERNEL_MARCH_PAIRS, -4},
-                             {RLBM_KERNEL_MARCH2, 0}, {RLBM_KERNEL_MARCH2, -1}};
+                             {RLBM_KERNEL_MARCH2, 0},  {RLBM_KERNEL_MARCH2, 8},
+                             {RLBM_KERNEL_MARCH2, 16}, {RLBM_KERNEL_MARCH2, 24},
+                             {RLBM_KERNEL_MARCH2, 32}};
     int auto_seg[5] = {0, 0, 0, 0, 0};
-    int tried[17][2];
+    int tried[20][2];
     int n_tried = 0;
     const bool bits16 = E.storage == RLBM_F16S || E.storage == RLBM_BF16S;
     int rc = RLBM_OK;

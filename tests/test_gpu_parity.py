@@ -280,6 +280,17 @@ def test_two_step_form_graph_replay_and_checkpoint(chunk):
     del junk
 
 
+def test_two_step_form_default_segment():
+    """Parameter 0 of the two-step form is a 12-row segment (its measured best
+    on lattices much larger than the caches), also on a lattice shorter than
+    that, which then runs as one segment per strip."""
+    for ny in (64, 8):
+        lat = rl.Lattice(256, ny, 0.6, storage="F32")
+        lat.set_kernel("march2", 0)
+        assert lat.kernel() == ("march2", 12)
+        lat.close()
+
+
 def test_autotune_keeps_results_bitwise():
     """The autotuner (lattice and ensemble) tries every form while stepping;
     the state after it equals plain tile-form stepping by the same count."""
