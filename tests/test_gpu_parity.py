@@ -411,6 +411,32 @@ def test_unstable_state_is_flagged():
     assert lat.check() == rl.EUNSTABLE
 
 
+@pytest.mark.parametrize("storage", ["F64", "F32", "F16S", "BF16S"])
+def test_circ8_kernel_forms_are_bitwise_equal(storage):
+    """The 8-direction stencil through every kernel form (ragged 130 x 37
+    lattice: a 2-column last strip, segments that do not divide 37)."""
+    nx, ny = 130, 37
+    e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=9)
+    fr = rl.Forcing(1e-4, 2.0, 5.0, 6)
+    forms = [("tile", 1), ("tile", 4), ("staged", 4), ("march", 0), ("march", 3),
+             ("march2", 0), ("march2", 5)]
+    if storage in ("F16S", "BF16S"):
+        forms += [("march_pairs", 0), ("march_pairs", 3)]
+    ref = None
+    for kind, param in forms:
+        lat = rl.Lattice(nx, ny, 0.6, stencil="CIRC8", storage=storage, forcing=fr)
+        lat.set_kernel(kind, param)
+        lat.set_state(dev(e), dev(bx), dev(by))
+        lat.step(7)
+        assert lat.check() == rl.OK
+        F = host(lat.populations())
+        lat.close()
+        if ref is None:
+            ref = F
+        else:
+            assert np.array_equal(F, ref), (kind, param)
+
+
 def test_circ8_parity():
     st = ostencil.circ8()
     F0 = workloads.random_populations(st.v, 20, 36, seed=3, spread=0.3, z_mirror=False)

@@ -102,7 +102,8 @@ def test_fold_kernel_forms_are_bitwise_equal(storage):
     e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=4)
     fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
     ref = None
-    forms = [("tile", 1), ("tile", 4), ("staged", 4), ("march", 0), ("march", 3), ("march", 500)]
+    forms = [("tile", 1), ("tile", 4), ("staged", 4), ("march", 0), ("march", 3), ("march", 500),
+             ("march2", 0), ("march2", 4)]
     if storage == "F16S":
         forms += [("march_pairs", 0), ("march_pairs", 3), ("march_pairs", 500)]
     for kind, param in forms:
