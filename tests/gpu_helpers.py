@@ -80,11 +80,12 @@ def sample_sites(nx, ny, n, seed):
     return np.array(xs), np.array(ys)
 
 
-def gather_patches(F_dev, xs, ys):
-    """(Q, S, 3, 3) FP64 patches of a device population tensor around sites."""
+def gather_patches(F_dev, xs, ys, radius=1):
+    """(Q, S, w, w) FP64 patches, w = 2 radius + 1, of a device population
+    tensor around sites (periodic)."""
     t = torch()
     Q, ny, nx = F_dev.shape
-    dx = t.tensor([-1, 0, 1], device=F_dev.device)
+    dx = t.arange(-radius, radius + 1, device=F_dev.device)
     X = (t.as_tensor(xs, device=F_dev.device)[:, None] + dx[None, :]) % nx    # (S, 3)
     Y = (t.as_tensor(ys, device=F_dev.device)[:, None] + dx[None, :]) % ny
     P = F_dev[:, Y[:, :, None], X[:, None, :]]                                 # (Q, S, 3, 3)
@@ -119,6 +120,44 @@ def oracle_step_at(patches, st, tau, cfl, force=None, step_index=0, sites=None, 
             Fn = Fn + orlbm.force_source(T, R, fx, fy, cfl, st)
         out[:, s] = Fn[:, 1, 1]
     return out
+
+
+def oracle_two_steps_at(patches, st, tau, cfl, force, step_index, sites, nxy, realization=0):
+    """Oracle result of two steps at the centre of each 5x5 patch (oracle
+    order): one step on the whole window is exact on its inner 3x3 (a site
+    pulls from its 3x3 neighbourhood, cfl <= 1), a second step on that 3x3 is
+    exact at its centre.  The force is evaluated at every site of each window,
+    at steps step_index and step_index + 1."""
+    Q, S = patches.shape[:2]
+    xs, ys = (np.asarray(v) for v in sites)
+    nx, ny = nxy
+    F = patches                                                 # (Q, S, w, w)
+    for k in (0, 1):
+        w = F.shape[2]
+        r = w // 2
+        d = np.arange(-r, r + 1)
+        X = (xs[:, None, None] + d[None, None, :]) % nx         # (S, 1, w)
+        Y = (ys[:, None, None] + d[None, :, None]) % ny         # (S, w, 1)
+        X, Y = np.broadcast_arrays(X, Y)
+        fx = fy = None
+        if force is not None and force["amplitude"] != 0.0:
+            fx, fy = oforcing.force_at(nx, ny, force["amplitude"], force["k_lo"], force["k_hi"],
+                                       force["seed"], step_index + k, X.ravel(), Y.ravel(),
+                                       realization)
+            fx, fy = fx.reshape(S, w, w), fy.reshape(S, w, w)
+        out = np.empty((Q, S, w - 2, w - 2))
+        for s in range(S):
+            Fs = orlbm.stream(F[:, s], st, cfl)
+            T, R = orlbm.moments(Fs, st)
+            eps, u = orlbm.landau(T)
+            beta = u[1:] / u[0]
+            Feq = orlbm.equilibrium(eps, beta, st)
+            Fn = orlbm.collide(Fs, Feq, beta, tau, st)
+            if fx is not None:
+                Fn = Fn + orlbm.force_source(T, R, fx[s], fy[s], cfl, st)
+            out[:, s] = Fn[:, 1:-1, 1:-1]
+        F = out
+    return F[:, :, 0, 0]
 
 
 def fold_maps():

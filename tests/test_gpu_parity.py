@@ -19,7 +19,8 @@ from oracle import stencil as ostencil
 import workloads
 
 from gpu_helpers import (dev, field_errors, gather_patches, gpu_fields, host, lib_to_oracle,
-                         oracle_step_at, oracle_to_lib, rel, sample_sites, say)
+                         oracle_step_at, oracle_to_lib, oracle_two_steps_at, rel, sample_sites,
+                         say)
 
 pytestmark = pytest.mark.gpu
 
@@ -134,23 +135,29 @@ def test_forced512_short_horizon_reduced_storage(storage, tol_eps, tol_beta):
     assert errs["beta_x"] < tol_beta and errs["beta_y"] < tol_beta
 
 
-@pytest.mark.parametrize("storage,n,shell,amp,tau", [
-    ("F32", 2048, (8.0, 12.0), 1e-5, 0.52),
-    ("F16S", 2048, (8.0, 12.0), 1e-5, 0.52),
-    ("BF16S", 2048, (8.0, 12.0), 1e-5, 0.52),
-    ("F32", 8192, (32.0, 40.0), 2e-6, 0.505),
-    ("F16S", 8192, (32.0, 40.0), 2e-6, 0.505),
+@pytest.mark.parametrize("storage,n,shell,amp,tau,form", [
+    ("F32", 2048, (8.0, 12.0), 1e-5, 0.52, None),
+    ("F16S", 2048, (8.0, 12.0), 1e-5, 0.52, None),
+    ("BF16S", 2048, (8.0, 12.0), 1e-5, 0.52, None),
+    ("BF16S", 2048, (8.0, 12.0), 1e-5, 0.52, ("march_pairs", 0)),
+    ("F32", 8192, (32.0, 40.0), 2e-6, 0.505, None),
+    ("F16S", 8192, (32.0, 40.0), 2e-6, 0.505, None),
+    ("F16S", 8192, (32.0, 40.0), 2e-6, 0.505, ("march_pairs", 0)),
 ])
-def test_full_size_sampled_one_step(storage, n, shell, amp, tau):
-    """Full-size workloads in the benchmark's launch configuration: after a
-    few steps, one more step is checked at sampled sites (incl. the four
-    corners) against the oracle applied to the 3x3 neighbourhood."""
+def test_full_size_sampled_one_step(storage, n, shell, amp, tau, form):
+    """Full-size workloads in the benchmark's launch configurations (the
+    library's default form, and the paired form the benchmark's autotuner
+    picks for 16-bit storage at 8192^2): after a few steps, one more step is
+    checked at sampled sites (incl. the four corners) against the oracle
+    applied to the 3x3 neighbourhood."""
     import torch
-    say("full size", storage, n)
+    say("full size", storage, n, form)
     sigma, seed = (0.005, 1) if n == 2048 else (0.002, 3)
     e, bx, by = workloads.noisy_rest(n, n, sigma, seed)
     fr = rl.Forcing(amp, shell[0], shell[1], 2)
     lat = rl.Lattice(n, n, tau, storage=storage, forcing=fr)
+    if form is not None:
+        lat.set_kernel(*form)
     lat.set_graph_chunk(8)
     lat.set_state(dev(e), dev(bx), dev(by))
     del e, bx, by
@@ -178,6 +185,48 @@ def test_full_size_sampled_one_step(storage, n, shell, amp, tau):
     assert lat.check() == rl.OK
     lat.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,shell,amp,tau,seg", [
+    (2048, (8.0, 12.0), 1e-5, 0.52, 12),
+    (8192, (32.0, 40.0), 2e-6, 0.505, 16),
+])
+def test_full_size_sampled_two_step_form(n, shell, amp, tau, seg):
+    """The two-step form at full size with FP32 storage, as the benchmark's
+    autotuner runs it: after 8 steps (4 launches), one more launch is checked
+    at sampled sites (incl. the four corners) against two oracle steps on the
+    5x5 neighbourhood.  Bound: twice the one-step bound."""
+    import torch
+    say("full size two-step", n, seg)
+    sigma, seed = (0.005, 1) if n == 2048 else (0.002, 3)
+    e, bx, by = workloads.noisy_rest(n, n, sigma, seed)
+    fr = rl.Forcing(amp, shell[0], shell[1], 2)
+    lat = rl.Lattice(n, n, tau, storage="F32", forcing=fr)
+    lat.set_kernel("march2", seg)
+    lat.set_graph_chunk(8)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    del e, bx, by
+    lat.step(8)
+    assert lat.kernel() == ("march2", seg)
+    xs, ys = sample_sites(n, n, 48, seed=n + 1)
+    F_before = lat.populations()
+    P = gather_patches(F_before, xs, ys, radius=2)
+    del F_before
+    torch.cuda.empty_cache()
+    lat.step(2)
+    F_after = lat.populations()
+    got = host(F_after[:, torch.as_tensor(ys, device="cuda:0"), torch.as_tensor(xs, device="cuda:0")])
+    del F_after
+    torch.cuda.empty_cache()
+    P_or = lib_to_oracle(P.reshape(P.shape[0], -1)).reshape(P.shape)
+    want = oracle_two_steps_at(P_or, SPH, tau, 1.0,
+                               dict(amplitude=amp, k_lo=shell[0], k_hi=shell[1], seed=2),
+                               8, (xs, ys), (n, n))
+    d = np.abs(lib_to_oracle(got) - want)
+    say("max |dF|", d.max())
+    assert np.all(d <= 8e-6)
+    assert lat.check() == rl.OK
+    lat.close()
 
 
 @pytest.mark.parametrize("storage", ["F64", "F32", "F16S", "BF16S"])
