@@ -329,6 +329,42 @@ def test_two_step_form_graph_replay_and_checkpoint(chunk):
     del junk
 
 
+def test_full_ensemble_in_benchmark_configuration():
+    """The 256-lattice ensemble workload (sides 64/128/256, tau in [0.51, 0.8],
+    FP32, forcing shell [2, 4] with counter word r) in the form the
+    benchmark's autotuner picks for it (two-step, 8-row segments): after 4
+    steps, realizations of every side against the oracle, every population
+    (4 x the one-step FP32 bound)."""
+    import torch
+    spec = workloads.ensemble()
+    sizes = [(n, n) for n, _ in spec]
+    taus = [t for _, t in spec]
+    frs = [rl.Forcing(1e-5, 2.0, 4.0, r) for r in range(len(spec))]
+    ens = rl.Ensemble(sizes, taus, storage="F32", forcings=frs)
+    inits = []
+    for r, (n, _) in enumerate(spec):
+        e, bx, by = workloads.noisy_rest(n, n, 0.005, seed=r)
+        inits.append((e, bx, by))
+        ens.set_state(r, dev(e), dev(bx), dev(by))
+    ens.set_kernel("march2", 8)
+    ens.set_graph_chunk(2)
+    ens.step(4)
+    assert ens.check() == rl.OK
+    picked = {}
+    for r, (n, _) in enumerate(spec):           # the first realization of each side, and the last
+        picked.setdefault(n, r)
+    for r in sorted(set(picked.values()) | {len(spec) - 1}):
+        n, tau = spec[r]
+        F = orlbm.run(orlbm.set_state(*inits[r], SPH), SPH, tau, 4,
+                      force=dict(amplitude=1e-5, k_lo=2.0, k_hi=4.0, seed=r), realization=r)
+        got = lib_to_oracle(host(ens.populations(r)))
+        d = float(np.abs(got - F).max())
+        say("ensemble", r, n, tau, "max |dF|", d)
+        assert d <= 1.6e-5
+    ens.close()
+    torch.cuda.empty_cache()
+
+
 def test_two_step_form_default_segment():
     """Parameter 0 of the two-step form is a 12-row segment (its measured best
     on lattices much larger than the caches), also on a lattice shorter than
