@@ -278,8 +278,8 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  * rlbm_autotune times the tile heights, the staged form, five segment lengths
  * of the row-marching form (the automatic one and 1/2, 3/4, 3/2 and 2 times
  * it; a length two of them share is timed once), the same five of the paired
- * form for 16-bit storage, and the two-step form with segments of 8, 12,
- * 16, 24 and 32 rows, for `steps` steps each (advancing the state) and keeps
+ * form for 16-bit storage, and the two-step form with segments of 8, 10, 12,
+ * 16, 18, 20, 24 and 32 rows, for `steps` steps each (advancing the state) and keeps
  * the fastest; *h_th receives th, or minus the segment length for a
  * marching form.                                                           */
 enum {

@@ -1114,8 +1114,9 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     // segments 2x (-1), 3/2 x (-2), 1/2 x (-3) and 3/4 x (-4) as long; which
     // of these runs fastest depends on how the rounds of segments fill the
     // chip (measured: 16-bit storage at 2048^2, 105 us at 8 rows, 127 us at 11);
-    // the two-step form with segments of 12 (its default), 8, 16, 24, 32 rows
-    const int cand[20][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
+    // the two-step form with segments of 12 (its default), 8, 10, 16, 18, 20,
+    // 24 and 32 rows (FP32 2048^2: 149 us at 18 rows, 152 at 12, 170 at 15)
+    const int cand[23][2] = {{RLBM_KERNEL_TILE, 1},   {RLBM_KERNEL_TILE, 2},
                              {RLBM_KERNEL_TILE, 4},   {RLBM_KERNEL_TILE, 8},
                              {RLBM_KERNEL_STAGED, 4},
                              {RLBM_KERNEL_MARCH, 0},  {RLBM_KERNEL_MARCH, -1},
@@ -1125,10 +1126,11 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
                              {RLBM_KERNEL_MARCH_PAIRS, -2}, {RLBM_KERNEL_MARCH_PAIRS, -3},
                              {RLBM_KERNEL_MARCH_PAIRS, -4},
                              {RLBM_KERNEL_MARCH2, 0},  {RLBM_KERNEL_MARCH2, 8},
-                             {RLBM_KERNEL_MARCH2, 16}, {RLBM_KERNEL_MARCH2, 24},
-                             {RLBM_KERNEL_MARCH2, 32}};
+                             {RLBM_KERNEL_MARCH2, 10}, {RLBM_KERNEL_MARCH2, 16},
+                             {RLBM_KERNEL_MARCH2, 18}, {RLBM_KERNEL_MARCH2, 20},
+                             {RLBM_KERNEL_MARCH2, 24}, {RLBM_KERNEL_MARCH2, 32}};
     int auto_seg[5] = {0, 0, 0, 0, 0};
-    int tried[20][2];
+    int tried[23][2];
     int n_tried = 0;
     const bool bits16 = E.storage == RLBM_F16S || E.storage == RLBM_BF16S;
     int rc = RLBM_OK;
