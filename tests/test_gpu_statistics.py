@@ -66,3 +66,29 @@ def test_time_averaged_spectrum_and_enstrophy_match_f64():
         # the means, plus the relative precision of the stored deviation
         assert dE <= 3 * (_se(E) + _se(ref_E)) + rel_tol * ref_E.mean()
         assert dZ <= 3 * (_se(Z) + _se(ref_Z)) + rel_tol * ref_Z.mean()
+
+
+def test_kernel_forms_stay_bitwise_equal_over_a_long_run():
+    """The 512^2 forced workload over 3000 steps in every kernel form, with
+    graph replay: the forms compute the same bits at every site and step, so
+    the chaotic trajectories stay identical (FP32 and F16S storage)."""
+    wl = workloads.WORKLOADS["forced512"]
+    A, klo, khi, seed = wl.forcing
+    e, bx, by = workloads.initial_fields(wl)
+    for storage, forms in (("F32", [("tile", 4), ("tile", 1), ("staged", 4), ("march", 2), ("march2", 8)]),
+                           ("F16S", [("tile", 4), ("march", 2), ("march_pairs", 2), ("march2", 8)])):
+        ref = None
+        for kind, param in forms:
+            lat = rl.Lattice(wl.n, wl.n, wl.tau, storage=storage, forcing=rl.Forcing(A, klo, khi, seed))
+            lat.set_kernel(kind, param)
+            lat.set_state(dev(e), dev(bx), dev(by))
+            lat.set_graph_chunk(50)
+            lat.step(3000)
+            assert lat.check() == rl.OK
+            F = lat.populations().cpu().numpy()
+            lat.close()
+            if ref is None:
+                ref = F
+            else:
+                say(storage, kind, param, "max |dF| vs", forms[0], float(np.abs(F - ref).max()))
+                assert np.array_equal(F, ref), (storage, kind, param)
