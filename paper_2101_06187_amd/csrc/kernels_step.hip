@@ -670,11 +670,12 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
 // but every lane owns two adjacent columns (2 l, 2 l + 1) of a 128-column
 // strip: each load and store moves one 32-bit pair, so a wavefront's memory
 // instruction carries 256 bytes -- as many as in the FP32 form -- instead of
-// 128.  The window holds the pairs packed.  Horizontal neighbours: the
-// left neighbour of column 2 l is the high half of lane l - 1's pair, the
-// right neighbour of column 2 l + 1 the low half of lane l + 1's pair (one
-// lane exchange serves both columns); the other two are the lane's own
-// halves; the strip's edge columns take the halo columns as in march_kernel.
+// 128.  The window holds the pairs packed.  Horizontal neighbours: for a
+// population with c_x > 0 column 2 l takes the high half of lane l - 1's pair
+// and column 2 l + 1 the lane's own low half; with c_x < 0 column 2 l + 1
+// takes the low half of lane l + 1's pair and column 2 l the own high half --
+// one lane exchange per population; the strip's edge columns take the halo
+// columns as in march_kernel.
 // Both sites of a lane go through the same update_site as every other form,
 // so the results are bitwise identical.
 // The lane computes column A, then column B, so one site's streamed
