@@ -237,8 +237,9 @@ struct Engine {
         cfg[1].seglen_req = 0;
     }
 
-    // work items (tiles of 64 x th sites, or strip segments of 64 (62 for the
-    // two-step kernel) columns x seglen rows), their maps, the persistent grid
+    // work items (tiles of 64 x th sites, or strip segments of 64 columns --
+    // 62 for the two-step kernel, 128 for the paired kernel -- x seglen rows),
+    // their maps, the persistent grid
     int configure_map(int m) {
         Cfg& c = cfg[m];
         if (c.kind != kKernelTile) c.th = 4;          // 4 wavefronts per block (kStageTH)
