@@ -2,12 +2,15 @@
 // stirring force of Sec. III C / App. B), one translation unit per storage
 // form, selected by RLBM_STORAGE_ID at compile time.
 //
-// Three forms of the same per-site update (update_site in site.hpp):
-//   step_kernel   -- one thread owns one lattice site; a block is a tile of
-//                    64 x th sites (one wavefront per tile row);
-//   march_kernel  -- a wavefront marches down a 64-column strip segment with a
-//                    rolling register window of rows;
-//   march2_kernel -- the same for two time steps per launch.
+// Five forms of the same per-site update (update_site in site.hpp):
+//   step_kernel       -- one thread owns one lattice site; a block is a tile
+//                        of 64 x th sites (one wavefront per tile row);
+//   staged_kernel     -- the same tile with every population row it needs
+//                        staged in LDS once;
+//   march_kernel      -- a wavefront marches down a 64-column strip segment
+//                        with a rolling register window of rows;
+//   march_pair_kernel -- the same with two columns per lane (16-bit storage);
+//   march2_kernel     -- the marching form for two time steps per launch.
 // Grids are persistent: block b walks the work items of the chunk that belongs
 // to its XCD (b mod 8), so adjacent tiles -- which share halo cache lines --
 // are served by the same L2.  Per site, in registers:
