@@ -429,6 +429,38 @@ def test_checkpoint_resume_is_bitwise():
         c.load(blob)
 
 
+@pytest.mark.parametrize("storage,first,second", [
+    ("F32", ("march2", 4), ("tile", 4)),
+    ("F32", ("tile", 1), ("march2", 3)),
+    ("F16S", ("march2", 4), ("march_pairs", 3)),
+    ("BF16S", ("march_pairs", 0), ("march", 2)),
+])
+def test_checkpoint_resume_across_kernel_forms(storage, first, second):
+    """A checkpoint taken by one kernel form after an odd number of steps (the
+    two-step form ends with a one-step launch) and resumed by another equals
+    uninterrupted stepping bitwise: the state, the step count, the buffer
+    parity and the force-table ring carry over between forms."""
+    nx, ny = 130, 37
+    e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=21)
+    fr = rl.Forcing(1e-4, 2.0, 5.0, 14)
+    ref = rl.Lattice(nx, ny, 0.58, storage=storage, forcing=fr)
+    ref.set_kernel("tile", 4)
+    ref.set_state(dev(e), dev(bx), dev(by))
+    ref.step(16)
+    a = rl.Lattice(nx, ny, 0.58, storage=storage, forcing=fr)
+    a.set_kernel(*first)
+    a.set_state(dev(e), dev(bx), dev(by))
+    a.step(7)
+    blob = a.save()
+    a.close()
+    b = rl.Lattice(nx, ny, 0.58, storage=storage, forcing=fr)
+    b.set_kernel(*second)
+    b.load(blob)
+    assert b.steps == 7
+    b.step(9)
+    assert np.array_equal(host(b.populations()), host(ref.populations()))
+
+
 def test_conserved_matches_oracle():
     e, bx, by = workloads.noisy_rest(48, 80, 0.02, seed=2)
     lat = rl.Lattice(80, 48, 0.7, storage="F64")
