@@ -69,7 +69,8 @@ def test_eta_s_kernel_forms_bitwise(storage):
     e = e * np.linspace(0.7, 1.6, nx)[None, :]
     fr = rl.Forcing(1e-4, 2.0, 5.0, 3)
     ref = None
-    forms = [("tile", 1), ("tile", 4), ("staged", 4), ("march", 0), ("march", 3)]
+    forms = [("tile", 1), ("tile", 4), ("staged", 4), ("march", 0), ("march", 3),
+             ("march2", 0), ("march2", 4)]
     if storage == "F16S":
         forms += [("march_pairs", 0), ("march_pairs", 3)]
     for kind, param in forms:
