@@ -304,7 +304,8 @@ class Lattice:
     def set_kernel(self, kind, param=0):
         """kind "tile" (param = tile height 1/2/4/8), "staged" (param 4),
         "march", "march_pairs" (16-bit storage) or "march2" (param = rows per
-        strip segment, 0 = automatic)."""
+        strip segment; 0 = about one segment per resident wavefront for the
+        one-step forms, 12 rows for "march2")."""
         _check(lib().rlbm_set_kernel(self._ctx, KERNELS[kind], int(param)))
 
     def kernel(self):
