@@ -1078,12 +1078,14 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         // step-s rows r0 .. r1 feed the outputs ya .. yb - 1
         const int r0 = ya - 1, r1 = yb;
         T cur[Q], up[M::nU], dn[M::nD];           // input rows rr, rr - 1, rr + 1
+        T nxt[Q];                                 // in flight: rr + 1 (c_y >= 0), rr + 2 (c_y < 0)
         T sc[Q], su[M::nU];                       // step-s rows rr - 1 (all), rr - 2 (c_y > 0)
         sfor<0, Q>([&](auto iq) {
             constexpr int q = decltype(iq)::value;
             cur[q] = ld(q, r0);
             if constexpr (M::cy(q) > 0) up[M::uidx(q)] = ld(q, r0 - 1);
             if constexpr (M::cy(q) < 0) dn[M::didx(q)] = ld(q, r0 + 1);
+            nxt[q] = ld(q, M::cy(q) < 0 ? r0 + 2 : r0 + 1);
         });
         T hp = gather(r0 - 1);
         T hc = gather(r0);
@@ -1122,21 +1124,28 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                     }
                 }
             });
-            // the input window moves down one row now: its loads are in
-            // flight while the second step below is computed
+            // the input window moves down one row now, from the row loaded one
+            // iteration ago; the row after it is loaded now, so every load
+            // has two rows of both steps' work to arrive
             if (rr < r1) {
                 sfor<0, Q>([&](auto iq) {
                     constexpr int q = decltype(iq)::value;
                     if constexpr (M::cy(q) > 0) {
                         up[M::uidx(q)] = cur[q];
-                        cur[q] = ld(q, rr + 1);
+                        cur[q] = nxt[q];
                     } else if constexpr (M::cy(q) < 0) {
                         cur[q] = dn[M::didx(q)];
-                        dn[M::didx(q)] = ld(q, rr + 2);
+                        dn[M::didx(q)] = nxt[q];
                     } else {
-                        cur[q] = ld(q, rr + 1);
+                        cur[q] = nxt[q];
                     }
                 });
+                if (rr + 1 < r1) {
+                    sfor<0, Q>([&](auto iq) {
+                        constexpr int q = decltype(iq)::value;
+                        nxt[q] = ld(q, M::cy(q) < 0 ? rr + 3 : rr + 2);
+                    });
+                }
                 hp = hc;
                 hc = hn;
                 hn = gather(rr + 2);
