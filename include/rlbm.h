@@ -263,7 +263,9 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
  *                         population is read and written once per two steps;
  *                         param = rows per strip segment, 0 = 12 rows.  An
  *                         odd step count ends with one launch of the
- *                         one-step form.
+ *                         one-step form.  Needs ny >= 3 on every lattice
+ *                         (EUNSUPPORTED otherwise; the autotuner then skips
+ *                         it).
  * By default the library uses RLBM_KERNEL_MARCH (param 0) for FP32, F16S and
  * BF16S storage when every resident wavefront gets a segment of at least 8
  * rows, and RLBM_KERNEL_TILE with th = 4 otherwise; RLBM_KERNEL_STAGED and

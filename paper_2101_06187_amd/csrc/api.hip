@@ -1061,6 +1061,10 @@ int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
             E.cfg[0].seglen_req = param;
             E.pairs = false;
         } else {
+            // the two-step form reads input rows up to two past a segment's
+            // last row and wraps them by one period: every lattice needs ny >= 3
+            for (const rlbm_lattice& l : E.lats)
+                if (l.ny < 3) return fail(RLBM_EUNSUPPORTED, "the two-step form needs ny >= 3");
             E.cfg[1].kind = kKernelMarch2;
             E.cfg[1].seglen_req = param;
             E.pairs = true;
@@ -1134,10 +1138,13 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     int tried[23][2];
     int n_tried = 0;
     const bool bits16 = E.storage == RLBM_F16S || E.storage == RLBM_BF16S;
+    int min_ny = 65536;
+    for (const rlbm_lattice& l : E.lats) min_ny = std::min(min_ny, (int)l.ny);
     int rc = RLBM_OK;
     for (const auto& c : cand) {
         if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
         if (c[0] == RLBM_KERNEL_MARCH_PAIRS && !bits16) continue;
+        if (c[0] == RLBM_KERNEL_MARCH2 && min_ny < 3) continue;
         const int a = auto_seg[c[0]];
         int param = c[1];
         if (c[1] < 0) {

@@ -67,6 +67,59 @@ def test_longest_side_one_step(shape):
         lat.close()
 
 
+@pytest.mark.parametrize("shape,forced", [((65536, 3), False), ((130, 3), True), ((70, 4), False)])
+def test_two_step_form_fewest_rows(shape, forced):
+    """The two-step form on the fewest rows it accepts: its input window
+    reaches two rows past a segment on either side, wrapped by one period.
+    Two steps of random populations, one segment, one-row and ragged
+    segments, against the oracle."""
+    nx, ny = shape
+    force = dict(amplitude=3e-3, k_lo=1.0, k_hi=1.4, seed=5) if forced else None
+    fr = rl.Forcing(force["amplitude"], force["k_lo"], force["k_hi"], force["seed"]) if forced else None
+    F0 = workloads.random_populations(SPH.v, ny, nx, seed=nx + 3 * ny, spread=0.3)
+    F2o = orlbm.run(F0, SPH, 0.7, 2, cfl=0.9, force=force)
+    for param in (0, 1, 2):
+        say("two-step fewest rows", shape, forced, param)
+        lat = rl.Lattice(nx, ny, 0.7, storage="F64", cfl=0.9, forcing=fr)
+        lat.set_kernel("march2", param)
+        lat.set_populations(dev(oracle_to_lib(F0)))
+        lat.step(2)
+        err = rel(lib_to_oracle(host(lat.populations())), F2o)
+        say("err", err)
+        assert err < 1e-13
+        assert lat.check() == rl.OK
+        lat.close()
+
+
+def test_two_step_form_refused_below_three_rows():
+    """ny = 2 is below what the two-step form reads: EUNSUPPORTED from the
+    lattice and the ensemble; the autotuner leaves it out and keeps a form
+    whose results equal the tile form's."""
+    nx, ny = 130, 2
+    lat = rl.Lattice(nx, ny, 0.7, storage="F32")
+    with pytest.raises(rl.RlbmError) as ex:
+        lat.set_kernel("march2", 0)
+    assert ex.value.code == rl.EUNSUPPORTED
+    ens = rl.Ensemble([(64, 8), (64, 2)], [0.6, 0.7], storage="F32")
+    with pytest.raises(rl.RlbmError) as ex:
+        ens.set_kernel("march2", 0)
+    assert ex.value.code == rl.EUNSUPPORTED
+    ens.close()
+    e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=2)
+    lat.set_state(dev(e), dev(bx), dev(by))
+    kind, param = lat.autotune(4)
+    say("autotuned on ny = 2", kind, param, lat.steps)
+    assert kind != "march2"
+    ref = rl.Lattice(nx, ny, 0.7, storage="F32")
+    ref.set_kernel("tile", 1)
+    ref.set_state(dev(e), dev(bx), dev(by))
+    ref.step(lat.steps)
+    lat.step(3)
+    ref.step(3)
+    assert np.array_equal(host(lat.populations()), host(ref.populations()))
+    assert lat.check() == rl.OK
+
+
 def test_fast_flow_landau():
     """Populations with a strong one-sided momentum (|beta| up to ~0.5): the
     Landau solve takes several Newton passes; one step against the oracle."""
