@@ -1,5 +1,6 @@
 """Edge cases of the GPU path against the oracle or against exact expectations:
-zero steps, the rest state, the largest lattice side the ABI accepts, fast
+zero steps, the rest state, the largest lattice side the ABI accepts, the
+narrowest lattices of the two-step form (and its refusal below three rows), fast
 flows (many Newton passes in the Landau solve), tau close to 1/2, a forcing
 shell that holds no lattice mode, a one-lattice ensemble."""
 import numpy as np
@@ -67,10 +68,12 @@ def test_longest_side_one_step(shape):
         lat.close()
 
 
-@pytest.mark.parametrize("shape,forced", [((65536, 3), False), ((130, 3), True), ((70, 4), False)])
-def test_two_step_form_fewest_rows(shape, forced):
-    """The two-step form on the fewest rows it accepts: its input window
-    reaches two rows past a segment on either side, wrapped by one period.
+@pytest.mark.parametrize("shape,forced", [((65536, 3), False), ((130, 3), True), ((70, 4), False),
+                                          ((2, 4099), False), ((3, 67), True)])
+def test_two_step_form_narrow_lattices(shape, forced):
+    """The two-step form on the fewest rows it accepts (its input window
+    reaches two rows past a segment on either side, wrapped by one period)
+    and on lattices narrower than a strip (every lane's column wrapped).
     Two steps of random populations, one segment, one-row and ragged
     segments, against the oracle."""
     nx, ny = shape
@@ -79,7 +82,7 @@ def test_two_step_form_fewest_rows(shape, forced):
     F0 = workloads.random_populations(SPH.v, ny, nx, seed=nx + 3 * ny, spread=0.3)
     F2o = orlbm.run(F0, SPH, 0.7, 2, cfl=0.9, force=force)
     for param in (0, 1, 2):
-        say("two-step fewest rows", shape, forced, param)
+        say("two-step narrow", shape, forced, param)
         lat = rl.Lattice(nx, ny, 0.7, storage="F64", cfl=0.9, forcing=fr)
         lat.set_kernel("march2", param)
         lat.set_populations(dev(oracle_to_lib(F0)))
