@@ -596,12 +596,14 @@ def test_ensemble_matches_oracle(kind):
 @pytest.mark.parametrize("storage", ["F16S", "BF16S"])
 @pytest.mark.parametrize("shape,cfl,forced", [((96, 104), 1.0, True), ((130, 37), 1.0, True),
                                               ((37, 9), 0.9, True), ((200, 66), 0.9, False),
-                                              ((256, 20), 1.0, True)])
+                                              ((256, 20), 1.0, True), ((2, 33), 0.9, False),
+                                              ((3, 5), 1.0, False), ((129, 2), 1.0, False)])
 def test_paired_form_is_bitwise_equal_to_tile_form(storage, shape, cfl, forced):
     """The paired marching form (two columns per lane, 128-column strips) on
     ragged lattices -- the last strip 2, 37, 72 or 128 columns wide, one or
-    both columns of the last lane active, a single short strip -- equals the
-    tile form bit for bit over 5 steps, for several segment lengths."""
+    both columns of the last lane active, a single short strip, lattices of
+    2 and 3 columns or 2 rows -- equals the tile form bit for bit over 5
+    steps, for several segment lengths."""
     nx, ny = shape
     e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=nx + ny)
     # the driven shell 2 <= |k| <= 5, narrowed to stay below the Nyquist wave
