@@ -300,8 +300,12 @@ struct Engine {
         // when the tiles leave resident slots free, build the next force tables
         // on extra blocks that run alongside the tiles
         c.extra_blocks = 0;
-        if (any_forced && c.tile_blocks < slots)
+        if (any_forced && c.tile_blocks < slots) {
             c.extra_blocks = std::min(2 * c.n_gitems, slots - c.tile_blocks);
+            // the tile and staged forms of FP32 and 16-bit storage put them
+            // first: a multiple of 8 keeps every tile block on its XCD
+            if (tiled && storage != RLBM_F64 && c.extra_blocks >= 8) c.extra_blocks &= ~7;
+        }
         c.grid = c.tile_blocks + c.extra_blocks;
         return RLBM_OK;
     }

@@ -70,7 +70,11 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     // XCD-aware persistent schedule: XCD x = b mod 8 owns tiles
     // [x * chunk, (x + 1) * chunk); its nb blocks stride through them.
     const int G = A.tile_blocks;
-    const int b = blockIdx.x;
+    // The force-table blocks take the first block indices in the FP32 and
+    // 16-bit forms: a table item is a longer chain than a tile, and started
+    // first it ends within the tiles' single round (b < 0: a table block)
+    constexpr bool kTablesFirst = !F64;
+    const int b = kTablesFirst ? (int)blockIdx.x - ((int)gridDim.x - G) : (int)blockIdx.x;
     const int xcd = b & 7;
     const int nb = (G - xcd + 7) >> 3;
     const int chunk = (A.n_tiles + 7) >> 3;
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     const T* gtab = nullptr;
     int txi = 0, tyi = 0, t_prev = -1;
 
-    for (int t = b < G ? xcd * chunk + (b >> 3) : t_end; t < t_end; t += nb) {
+    for (int t = (kTablesFirst ? b >= 0 : b < G) ? xcd * chunk + (b >> 3) : t_end; t < t_end; t += nb) {
         const int r = A.tile_real ? uni((int)A.tile_real[t]) : 0;
         if (r != cur_r) {
             const RealDesc& Dsc = A.desc[r];
@@ -183,7 +187,8 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     // else the items of each XCD spread over its tile blocks
     if constexpr (FORCED) {
         const int extra = (int)gridDim.x - G;
-        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+        const int u0 = kTablesFirst ? (b < 0 ? b + extra : -1) : b - G;
+        build_force_tables<T>(A, step, extra > 0 ? u0 : xcd + 8 * (b >> 3),
                               extra > 0 ? extra : 8 * nb);
     }
 }
@@ -265,7 +270,11 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
 
     // XCD-aware persistent schedule, as in step_kernel
     const int G = A.tile_blocks;
-    const int b = blockIdx.x;
+    // The force-table blocks take the first block indices in the FP32 and
+    // 16-bit forms: a table item is a longer chain than a tile, and started
+    // first it ends within the tiles' single round (b < 0: a table block)
+    constexpr bool kTablesFirst = !F64;
+    const int b = kTablesFirst ? (int)blockIdx.x - ((int)gridDim.x - G) : (int)blockIdx.x;
     const int xcd = b & 7;
     const int nb = (G - xcd + 7) >> 3;
     const int chunk = (A.n_tiles + 7) >> 3;
@@ -297,7 +306,7 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
     const T* twp = nullptr;
     const T* gtab = nullptr;
 
-    for (int t = b < G ? xcd * chunk + (b >> 3) : t_end; t < t_end; t += nb) {
+    for (int t = (kTablesFirst ? b >= 0 : b < G) ? xcd * chunk + (b >> 3) : t_end; t < t_end; t += nb) {
         const int r = A.tile_real ? uni((int)A.tile_real[t]) : 0;
         if (r != cur_r) {
             const RealDesc& Dsc = A.desc[r];
@@ -388,7 +397,8 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
 
     if constexpr (FORCED) {
         const int extra = (int)gridDim.x - G;
-        build_force_tables<T>(A, step, extra > 0 ? b - G : xcd + 8 * (b >> 3),
+        const int u0 = kTablesFirst ? (b < 0 ? b + extra : -1) : b - G;
+        build_force_tables<T>(A, step, extra > 0 ? u0 : xcd + 8 * (b >> 3),
                               extra > 0 ? extra : 8 * nb);
     }
 }
