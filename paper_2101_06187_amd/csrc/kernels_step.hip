@@ -1085,11 +1085,15 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             return h;
         };
 
-        // step-s rows r0 .. r1 feed the outputs ya .. yb - 1
+        // step-s rows r0 .. r1 feed the outputs ya .. yb - 1.  Iteration rr
+        // first advances step s + 1 at row rr - 2 (from the step-s rows rr - 3,
+        // rr - 2, rr - 1 computed earlier) and stores it, then computes step s
+        // at row rr into registers: the stores are followed by a whole
+        // site update before the next row's loads are needed.
         const int r0 = ya - 1, r1 = yb;
         T cur[Q], up[M::nU], dn[M::nD];           // input rows rr, rr - 1, rr + 1
         T nxt[Q];                                 // in flight: rr + 1 (c_y >= 0), rr + 2 (c_y < 0)
-        T sc[Q], su[M::nU];                       // step-s rows rr - 1 (all), rr - 2 (c_y > 0)
+        T sa[M::nU], sb[Q], sp[Q];                // step-s rows rr - 3 (c_y > 0), rr - 2, rr - 1
         sfor<0, Q>([&](auto iq) {
             constexpr int q = decltype(iq)::value;
             cur[q] = ld(q, r0);
@@ -1101,7 +1105,42 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         T hc = gather(r0);
         T hn = gather(r0 + 1);
 
-        for (int rr = r0; rr <= r1; ++rr) {
+        for (int rr = r0; rr <= r1 + 1; ++rr) {
+            // step s + 1 at row rr - 2 from step-s rows rr - 3, rr - 2, rr - 1
+            if (rr >= ya + 2) {
+                T g[Q];
+                sfor<0, Q>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    constexpr Dir d = St::dir[q];
+                    constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
+                    const T own = sb[q];
+                    T vert = own;
+                    if constexpr (d.cy > 0) vert = sa[M::uidx(q)];
+                    if constexpr (d.cy < 0) vert = sp[q];
+                    if constexpr (d.cx == 0 && d.cy == 0) {
+                        g[q] = own;
+                    } else if constexpr (d.cx == 0) {
+                        if constexpr (UNIT && n == 1) g[q] = vert;
+                        else g[q] = lerp(own, vert, W.a[n - 1]);
+                    } else {
+                        const int addr = (lane - d.cx) * 4;
+                        const T own_nb = lane_from(own, addr);
+                        if constexpr (d.cy == 0) {
+                            if constexpr (UNIT && n == 1) g[q] = own_nb;
+                            else g[q] = lerp(own, own_nb, W.a[n - 1]);
+                        } else {
+                            const T vert_nb = lane_from(vert, addr);
+                            g[q] = fma(W.w11[n - 1], vert_nb,
+                                       fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                        }
+                    }
+                });
+                if (out_lane)
+                    update_site<S, St, FORCED>(g, c1x, cs, sn, rr - 2,
+                                               (gp<char>)(dst + (long long)(rr - 2) * rowq), colb,
+                                               A.d_flag);
+            }
+            if (rr > r1) break;
             // step s at row rr, every lane
             T f[Q];
             sfor<0, Q>([&](auto iq) {
@@ -1134,32 +1173,29 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                     }
                 }
             });
-            // the input window moves down one row now, from the row loaded one
-            // iteration ago; the row after it is loaded now, so every load
-            // has two rows of both steps' work to arrive
-            if (rr < r1) {
-                sfor<0, Q>([&](auto iq) {
-                    constexpr int q = decltype(iq)::value;
-                    if constexpr (M::cy(q) > 0) {
-                        up[M::uidx(q)] = cur[q];
-                        cur[q] = nxt[q];
-                    } else if constexpr (M::cy(q) < 0) {
-                        cur[q] = dn[M::didx(q)];
-                        dn[M::didx(q)] = nxt[q];
-                    } else {
-                        cur[q] = nxt[q];
-                    }
-                });
-                if (rr + 1 < r1) {
-                    sfor<0, Q>([&](auto iq) {
-                        constexpr int q = decltype(iq)::value;
-                        nxt[q] = ld(q, M::cy(q) < 0 ? rr + 3 : rr + 2);
-                    });
+            // The input window moves down one row now, from the row loaded one
+            // iteration ago, and the row after it is loaded now.  Loads past
+            // the rows the segment reads repeat its last rows (cache hits), so
+            // that every iteration issues the same loads.
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                if constexpr (M::cy(q) > 0) {
+                    up[M::uidx(q)] = cur[q];
+                    cur[q] = nxt[q];
+                } else if constexpr (M::cy(q) < 0) {
+                    cur[q] = dn[M::didx(q)];
+                    dn[M::didx(q)] = nxt[q];
+                } else {
+                    cur[q] = nxt[q];
                 }
-                hp = hc;
-                hc = hn;
-                hn = gather(rr + 2);
-            }
+            });
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                nxt[q] = ld(q, M::cy(q) < 0 ? min(rr + 3, r1 + 1) : min(rr + 2, r1));
+            });
+            hp = hc;
+            hc = hn;
+            hn = gather(min(rr + 2, r1));
             T fn[Q];
             update_site_to<S, St, FORCED>(
                 f, c0, cs, sn, wrap(rr),
@@ -1167,45 +1203,12 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                     fn[decltype(qc)::value] = (T)S::ld(&r);
                 },
                 A.d_flag);
-            // step s + 1 at row rr - 1 from step-s rows rr - 2, rr - 1, rr
-            if (rr >= ya + 1) {
-                T g[Q];
-                sfor<0, Q>([&](auto iq) {
-                    constexpr int q = decltype(iq)::value;
-                    constexpr Dir d = St::dir[q];
-                    constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
-                    const T own = sc[q];
-                    T vert = own;
-                    if constexpr (d.cy > 0) vert = su[M::uidx(q)];
-                    if constexpr (d.cy < 0) vert = fn[q];
-                    if constexpr (d.cx == 0 && d.cy == 0) {
-                        g[q] = own;
-                    } else if constexpr (d.cx == 0) {
-                        if constexpr (UNIT && n == 1) g[q] = vert;
-                        else g[q] = lerp(own, vert, W.a[n - 1]);
-                    } else {
-                        const int addr = (lane - d.cx) * 4;
-                        const T own_nb = lane_from(own, addr);
-                        if constexpr (d.cy == 0) {
-                            if constexpr (UNIT && n == 1) g[q] = own_nb;
-                            else g[q] = lerp(own, own_nb, W.a[n - 1]);
-                        } else {
-                            const T vert_nb = lane_from(vert, addr);
-                            g[q] = fma(W.w11[n - 1], vert_nb,
-                                       fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
-                        }
-                    }
-                });
-                if (out_lane)
-                    update_site<S, St, FORCED>(g, c1x, cs, sn, rr - 1,
-                                               (gp<char>)(dst + (long long)(rr - 1) * rowq), colb,
-                                               A.d_flag);
-            }
             // roll the step-s window
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
-                if constexpr (M::cy(q) > 0) su[M::uidx(q)] = sc[q];
-                sc[q] = fn[q];
+                if constexpr (M::cy(q) > 0) sa[M::uidx(q)] = sb[q];
+                sb[q] = sp[q];
+                sp[q] = fn[q];
             });
         }
     }
