@@ -32,3 +32,31 @@ def test_windows_match_whole_lattice(cfl):
                               (xs, ys), (nx, ny))
     assert np.abs(one - F1[:, ys, xs]).max() < 1e-14
     assert np.abs(two - F2[:, ys, xs]).max() < 1e-14
+
+
+def test_field_window_strip_matches_whole_lattice():
+    """The stored field references (tests/golden/make_field_windows.py):
+    windows of radius N + 1 side by side in one periodic strip, advanced N
+    forced steps, give the fields of the whole-lattice oracle run at their
+    centres."""
+    import importlib.util
+    import os
+    from oracle import diagnostics as odiag
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location(
+        "make_field_windows", os.path.join(here, "golden", "make_field_windows.py"))
+    mfw = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mfw)
+    wl = workloads.Workload("small", 40, 0.57, 3, "noise", 0.01, 5, (2e-3, 3.0, 6.0, 9))
+    xs, ys = [0, 39, 17, 5], [0, 39, 22, 31]
+    steps = 3
+    got = mfw.window_fields(wl, xs, ys, steps)
+    e, bx, by = workloads.initial_fields(wl)
+    force = dict(amplitude=2e-3, k_lo=3.0, k_hi=6.0, seed=9)
+    F = orlbm.run(orlbm.set_state(e, bx, by, SPH), SPH, wl.tau, steps, force=force)
+    eps, gx, gy, T6 = odiag.fields(F, SPH, 1.0)
+    want = {"eps": eps, "beta_x": gx, "beta_y": gy}
+    for i, name in enumerate(("T00", "T0x", "T0y", "Txx", "Txy", "Tyy")):
+        want[name] = T6[i]
+    for name, arr in want.items():
+        assert np.abs(np.asarray(got[name]) - arr[ys, xs]).max() < 1e-14, name
