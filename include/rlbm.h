@@ -184,7 +184,17 @@ int rlbm_fields(rlbm_ctx* ctx, double* d_e, double* d_ux, double* d_uy,
 int rlbm_conserved(rlbm_ctx* ctx, double h_out[3]);
 
 /* Populations as FP64 planes [Q][ny][nx] in the order of rlbm_stencil_info
- * (converted from / to the storage type).  For tests and tooling.          */
+ * (converted from / to the storage type).  For tests and tooling.
+ * The paper's lattice is one layer thick (Sec. V, N x N x 1), so its states
+ * are even under v_z -> -v_z, and the 26-direction step never forms the
+ * moments with a single z index (T^{0z}, T^{xz}, T^{yz}, which vanish on
+ * such states).  rlbm_set_populations therefore accepts only z-mirror
+ * symmetric input for RLBM_STENCIL_SPH26: F of direction (a, b, c) must equal
+ * F of (a, b, -c) at every site, bit for bit.  It checks this on the device
+ * first and returns RLBM_EINVAL, leaving the state unchanged, if any pair
+ * differs (or holds a NaN); the check synchronises the stream.  The folded
+ * stencil stores one population per mirror pair, and CIRC8 has no z
+ * component, so neither needs the check.                                   */
 int rlbm_get_populations(rlbm_ctx* ctx, double* d_out);
 int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in);
 
@@ -238,6 +248,18 @@ int rlbm_spectrum_average(const double* h_samples, int32_t n_samples, int32_t nb
 int rlbm_state_bytes(const rlbm_ctx* ctx, size_t* h_bytes);
 int rlbm_save(rlbm_ctx* ctx, void* h_buf, size_t bytes);
 int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
+
+/* Streaming copy of `bytes` bytes from d_src to d_dst on hip_stream (NULL:
+ * the null stream), `reps` times after one untimed copy, with 16-byte loads
+ * and stores and four loads in flight per thread over a persistent grid of 8
+ * blocks per compute unit.  *h_ms receives the mean duration of one copy in
+ * milliseconds (HIP events around the reps; synchronises).  A copy moves
+ * 2 * bytes through HBM when both buffers are larger than the caches: the
+ * practical streaming ceiling against which the step's bandwidth is read.
+ * EINVAL: NULL pointers, bytes or a pointer not a multiple of 16, reps < 1,
+ * overlapping buffers.  The buffers belong to the caller.                  */
+int rlbm_stream_copy(const void* d_src, void* d_dst, size_t bytes, int32_t reps,
+                     void* hip_stream, double* h_ms);
 
 /* Kernel form and launch shape.  Results never depend on them (bitwise).
  *   RLBM_KERNEL_TILE   -- every thread streams one site from global memory;

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("rlbm_set_graph_chunk", _I, [_P, _I32]),
     ("rlbm_set_relaxation", _I, [_P, _I32]),
     ("rlbm_profile_step_kernel", _I, [_P, _I64, _P]),
+    ("rlbm_stream_copy", _I, [_P, _P, _SZ, _I32, _P, _P]),
     ("rlbm_destroy", None, [_P]),
     ("rlbm_batch_workspace_bytes", _I, [_I32, _P, _I, _I, _P, _P]),
     ("rlbm_batch_init", _I, [_P, _I32, _P, _P, _I, _P, _I, _P, _SZ, _P]),
@@ -186,6 +187,19 @@ def _f64(t, shape):
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
         raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
     return t
+
+
+def stream_copy(src, dst, reps=10):
+    """Mean duration (ms) of one streaming copy of src (a CUDA tensor) into
+    dst (same size, no overlap) by the library's copy kernel: the practical
+    HBM streaming rate is 2 * bytes / time."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous CUDA tensors of the same size in bytes")
+    ms = ctypes.c_double()
+    _check(lib().rlbm_stream_copy(_ptr(src), _ptr(dst), nbytes, int(reps), _stream(src.device),
+                                  ctypes.byref(ms)))
+    return ms.value
 
 
 def spectrum_average(samples):

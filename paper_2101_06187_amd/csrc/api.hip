@@ -833,11 +833,57 @@ int rlbm_set_populations(rlbm_ctx* ctx, const double* d_in) {
     if (int rc = check_ctx(ctx)) return rc;
     if (!d_in) return fail(RLBM_EINVAL, "NULL input");
     Engine& E = ctx->e;
+    if (E.stencil == RLBM_STENCIL_SPH26) {
+        // the 26-direction step assumes z-mirror symmetric states
+        int* word = (int*)(E.ws + E.lay.ctl + 24);
+        HIPCHK(launch_mirror_check(d_in, E.lats[0].nx, E.lats[0].ny, word, E.stream));
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, word, sizeof(int), hipMemcpyDeviceToHost, E.stream));
+        HIPCHK(hipStreamSynchronize(E.stream));
+        if (bad)
+            return fail(RLBM_EINVAL, "populations are not z-mirror symmetric: F(a, b, c) must "
+                                     "equal F(a, b, -c) for every direction and site");
+    }
     HIPCHK(launch_reset(E.d_step, 0, E.flips, E.d_flag, E.stream));
     E.step = 0;
     HIPCHK(launch_set_populations(E.d_desc, 0, E.storage, E.stencil, E.lats[0].nx, E.lats[0].ny, d_in,
                                   E.parity(), E.stream));
     return E.prime_force_table();
+}
+
+int rlbm_stream_copy(const void* d_src, void* d_dst, size_t bytes, int32_t reps,
+                     void* hip_stream, double* h_ms) {
+    if (!d_src || !d_dst || !h_ms) return fail(RLBM_EINVAL, "NULL pointer");
+    if (bytes == 0 || bytes % 16 || (uintptr_t)d_src % 16 || (uintptr_t)d_dst % 16)
+        return fail(RLBM_EINVAL, "bytes and both pointers must be non-zero multiples of 16");
+    if (reps < 1) return fail(RLBM_EINVAL, "reps must be >= 1");
+    const char* a = (const char*)d_src;
+    const char* b = (const char*)d_dst;
+    if (a < b + bytes && b < a + bytes) return fail(RLBM_EINVAL, "buffers overlap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const long long n16 = (long long)(bytes / 16);
+    const int blocks = std::max(1, cus * 8);
+    HIPCHK(launch_stream_copy(d_src, d_dst, n16, blocks, s));     // warm-up
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RLBM_EHIP, "hipEventCreate failed");
+    }
+    hipError_t err = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && err == hipSuccess; ++i) err = launch_stream_copy(d_src, d_dst, n16, blocks, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(RLBM_EHIP, std::string("stream copy: ") + hipGetErrorString(err));
+    *h_ms = (double)ms / reps;
+    return RLBM_OK;
 }
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }

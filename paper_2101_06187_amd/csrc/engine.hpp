@@ -135,6 +135,9 @@ hipError_t launch_fields(const RealDesc* d_desc, int r, int storage, int stencil
                          int smode, int nx, int ny, int parity, double* e,
                          double* ux, double* uy, double* T, double2* z,
                          int* d_flag, hipStream_t s);
+hipError_t launch_mirror_check(const double* in, int nx, int ny, int* word, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, long long n16, int blocks,
+                              hipStream_t s);
 hipError_t launch_conserved(const RealDesc* d_desc, int r, int storage, int stencil,
                             int nx, int ny, int parity, double* partials,
                             int n_partials, double* out3, hipStream_t s);

@@ -493,6 +493,69 @@ struct ConservedFn {
     }
 };
 
+// ---------------------------------------------------------------------------
+// z-mirror symmetry of imported populations (26-direction stencil): the
+// one-layer lattice's states are even in v_z, and the step never forms the
+// moments with one z index, so a state whose mirror pairs (a, b, c) /
+// (a, b, -c) differ is outside what it computes.  Any differing pair (or a
+// NaN) sets *word to 1; *word is cleared first by clear_word_kernel.
+// ---------------------------------------------------------------------------
+__global__ void clear_word_kernel(int* word) {
+    if (threadIdx.x == 0) *(volatile int*)word = 0;
+}
+
+__global__ void mirror_check_kernel(const double* in, int nx, int ny, int* word) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    const long long plane = (long long)nx * ny;
+    const long long i = (long long)y * nx + x;
+    bool bad = false;
+    sfor<0, Sph26::Q>([&](auto iq) {
+        constexpr int q = decltype(iq)::value;
+        constexpr Dir d = Sph26::dir[q];
+        if constexpr (d.cz < 0) {
+            constexpr int m = mirror_of(q);
+            bad |= !(in[q * plane + i] == in[m * plane + i]);
+        }
+    });
+    if (bad) *(volatile int*)word = 1;
+}
+
+hipError_t launch_mirror_check(const double* in, int nx, int ny, int* word, hipStream_t s) {
+    hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, s, word);
+    hipLaunchKernelGGL(mirror_check_kernel, dim3((nx + 127) / 128, ny), dim3(128), 0, s, in, nx,
+                       ny, word);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy (measurement of the practical HBM ceiling): 16-byte elements,
+// four loads in flight per thread before the four stores, grid-stride over a
+// persistent grid.  n16 = bytes / 16.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) stream_copy_kernel(const float4* __restrict__ src,
+                                                          float4* __restrict__ dst, long long n16) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                     d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, long long n16, int blocks,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, s, (const float4*)src,
+                       (float4*)dst, n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_state(const RealDesc* d_desc, int r, int storage, int stencil, int nx,
                             int ny, const double* e, const double* ux, const double* uy,
                             int parity, hipStream_t s) {

@@ -126,4 +126,13 @@ constexpr double dir_comp(const Dir& d, int axis) {
     return c * comp_mag(n);
 }
 
+// Index of the z mirror (cx, cy, -cz) of direction q of the 26-direction set.
+constexpr int mirror_of(int q) {
+    for (int p = 0; p < Sph26::Q; ++p)
+        if (Sph26::dir[p].cx == Sph26::dir[q].cx && Sph26::dir[p].cy == Sph26::dir[q].cy &&
+            Sph26::dir[p].cz == -Sph26::dir[q].cz)
+            return p;
+    return -1;
+}
+
 }  // namespace rlbm

@@ -181,6 +181,61 @@ def test_one_lattice_ensemble_equals_lattice():
     assert np.array_equal(host(ens.populations(0)), host(lat.populations()))
 
 
+def _z_symmetrize(F):
+    """Copy every population with v_z > 0 onto its z mirror (library order)."""
+    v, _ = rl.stencil_info("SPH26")
+    for q in range(len(v)):
+        if v[q, 2] < 0:
+            m = int(np.argmin(np.abs(v - v[q] * np.array([1.0, 1.0, -1.0])).max(axis=1)))
+            F[q] = F[m]
+
+
+def test_set_populations_rejects_states_without_z_mirror_symmetry():
+    """The 26-direction step assumes F(a, b, c) = F(a, b, -c) (one-layer
+    lattice).  Input that breaks it in one value is refused with EINVAL and
+    leaves the stored state as it was; the folded and 8-direction stencils
+    take any input.  Only the library's own check reads the input."""
+    n = 24
+    F = workloads.random_populations(SPH.v, n, n, seed=5, spread=0.2)
+    lat = rl.Lattice(n, n, 0.6, storage="F64")
+    lat.set_populations(dev(oracle_to_lib(F)))
+    before = host(lat.populations())
+    v, _ = rl.stencil_info("SPH26")
+    q = int(np.flatnonzero(v[:, 2] < 0)[3])
+    bad = oracle_to_lib(F).copy()
+    bad[q, 7, 11] += 1e-12
+    with pytest.raises(rl.RlbmError) as ex:
+        lat.set_populations(dev(bad))
+    assert ex.value.code == rl.EINVAL
+    assert np.array_equal(host(lat.populations()), before)
+    bad[q, 7, 11] = np.nan
+    with pytest.raises(rl.RlbmError):
+        lat.set_populations(dev(bad))
+    lat.step(1)
+    assert lat.check() == rl.OK
+    # other stencils: no symmetry to check
+    for name in ("SPH26_ZFOLD", "CIRC8"):
+        L = rl.Lattice(n, n, 0.6, stencil=name, storage="F64")
+        G = 1.0 + 0.1 * np.random.default_rng(3).standard_normal((L.Q, n, n))
+        L.set_populations(dev(G))
+        assert np.array_equal(host(L.populations()), G)
+
+
+def test_stream_copy_probe():
+    """The library's streaming copy moves the bytes exactly and reports a
+    positive time; misuse is refused."""
+    import torch
+    a = torch.randn(1 << 22, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    ms = rl.stream_copy(a, b, reps=3)
+    assert ms > 0
+    assert torch.equal(a, b)
+    with pytest.raises(ValueError):
+        rl.stream_copy(a, b[:-1])
+    with pytest.raises(rl.RlbmError):
+        rl.stream_copy(a, a)
+
+
 def _bf16_rne(d32):
     """FP32 -> BF16 bits, round to nearest even (finite inputs)."""
     u = d32.view(np.uint32).astype(np.uint64)
@@ -202,6 +257,7 @@ def test_storage_rounding_is_round_to_nearest_even(storage):
     F.reshape(-1)[:ties.size] = 1.0 + ties.astype(np.float64)
     h16 = np.array([0x3C00 + 0x0400, 0x1001], dtype=np.uint16).view(np.float16)
     F.reshape(-1)[ties.size:ties.size + 2] = 1.0 + h16.astype(np.float64) + np.array([2.0 ** -22, -2.0 ** -22])
+    _z_symmetrize(F)          # the ties sit in population 0, which has v_z = 0
     lat = rl.Lattice(nx, ny, 0.7, storage=storage)
     lat.set_populations(dev(F))
     got = host(lat.populations())
