@@ -209,6 +209,19 @@ int rlbm_spectrum_scratch_bytes(const rlbm_ctx* ctx, size_t* h_bytes);
 int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
                   double* h_Ek, int32_t nbins, double* h_enstrophy);
 
+/* rlbm_spectrum without caller scratch, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid allocation): the scratch is a 33 MiB array in the library's device
+ * memory, one copy per GPU, held until the process ends.  Lattices up to
+ * 2^20 sites (nx * ny, both powers of two, e.g. 1024 x 1024); larger ones
+ * get RLBM_ENOSPACE.  The call allocates nothing; it must be made with the
+ * context's device current (EINVAL otherwise).  Calls on one GPU share the
+ * array: calls that overlap on one GPU (other threads, other contexts'
+ * streams) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero; each call overwrites what it reads.  Same results
+ * as rlbm_spectrum, synchronises.                                           */
+int rlbm_spectrum_static(rlbm_ctx* ctx, double* h_Ek, int32_t nbins, double* h_enstrophy);
+
 /* Velocity with the driven band removed (Sec. V: the recorded velocities are
  * filtered in Fourier space so that the driven wave numbers do not
  * contribute).  beta of the current fields (as rlbm_fields) is transformed,

@@ -82,6 +82,7 @@ SIGNATURES = [
     ("rlbm_set_populations", _I, [_P, _P]),
     ("rlbm_spectrum_scratch_bytes", _I, [_P, _P]),
     ("rlbm_spectrum", _I, [_P, _P, _SZ, _P, _I32, _P]),
+    ("rlbm_spectrum_static", _I, [_P, _P, _I32, _P]),
     ("rlbm_filtered_velocity", _I, [_P, _P, _SZ, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     ("rlbm_spectrum_average", _I, [_P, _I32, _I32, _P, _P]),
     ("rlbm_state_bytes", _I, [_P, _P]),
@@ -284,6 +285,14 @@ class Lattice:
         Z = ctypes.c_double()
         _check(lib().rlbm_spectrum(self._ctx, ctypes.c_void_p(p), n.value, Ek.ctypes.data_as(_P),
                                    nbins, ctypes.byref(Z)))
+        return Ek, Z.value
+
+    def spectrum_static(self, nbins):
+        """spectrum() through the allocation-free entry point (the library's
+        static device scratch; lattices up to 2^20 sites)."""
+        Ek = np.zeros(nbins)
+        Z = ctypes.c_double()
+        _check(lib().rlbm_spectrum_static(self._ctx, Ek.ctypes.data_as(_P), nbins, ctypes.byref(Z)))
         return Ek, Z.value
 
     def filtered_velocity(self, k_lo, k_hi):

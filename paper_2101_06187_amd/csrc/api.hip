@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -173,6 +174,7 @@ struct Engine {
     int smode = kStreamUnit;         // stream mode of the step kernels (all lattices)
     bool any_forced = false;
     int cus = 0;
+    int dev = 0;                     // device the engine was created on
     Cfg cfg[2];                      // [0] one step per launch, [1] two steps per launch
     bool pairs = false;              // advance pairs of steps with cfg[1]
     bool kind_auto = true;           // until rlbm_set_kernel / rlbm_set_tile / autotune
@@ -538,6 +540,7 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&E.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    E.dev = dev;
 
     E.d_step = (int64_t*)(E.ws + E.lay.ctl);
     E.d_flag = (int*)(E.ws + E.lay.ctl + 16);
@@ -981,6 +984,54 @@ int rlbm_spectrum(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double* 
     HIPCHK(hipStreamSynchronize(E.stream));
     if (h_enstrophy) *h_enstrophy = 0.5 * zz;
     return RLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free spectrum: the scratch of rlbm_spectrum in a file-scope
+// device array.  Each device that runs it holds its own copy of the array
+// (until the process ends); host code reaches a device's copy only through the
+// address hipGetSymbolAddress returns for that device, taken once per device
+// with the device current.  Every location the spectrum reads is written
+// earlier in the same call, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)33 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch array.
+static int static_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(RLBM_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RLBM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RLBM_OK;
+}
+
+int rlbm_spectrum_static(rlbm_ctx* ctx, double* h_Ek, int32_t nbins, double* h_enstrophy) {
+    if (int rc = check_ctx(ctx)) return rc;
+    Engine& E = ctx->e;
+    if (!h_Ek || nbins < 1) return fail(RLBM_EINVAL, "bad spectrum arguments");
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != E.dev) return fail(RLBM_EINVAL, "call with the context's device current");
+    size_t a, b, c, d, e, f;
+    int mb = 0;
+    const size_t need = spectrum_layout(E.lats[0].nx, E.lats[0].ny, &a, &b, &c, &d, &e, &f, &mb);
+    if (need > kStaticScratchBytes)
+        return fail(RLBM_ENOSPACE, "lattice too large for the static spectrum scratch "
+                                   "(33 MiB: at most 2^20 sites)");
+    void* p = nullptr;
+    if (int rc = static_scratch(cur, &p)) return rc;
+    return rlbm_spectrum(ctx, p, kStaticScratchBytes, h_Ek, nbins, h_enstrophy);
 }
 
 int rlbm_filtered_velocity(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes, double k_lo,
