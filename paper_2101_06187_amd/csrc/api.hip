@@ -82,6 +82,13 @@ int build_modes(const rlbm_lattice& lat, const rlbm_forcing* f, ModeTable& mt) {
     return RLBM_OK;
 }
 
+// Terms of the FP32 force sum per row: 2 (K + 1) rounded up to kForceTerms
+// (0 when the lattice is unforced).
+int force_terms(const ModeTable& mt) {
+    if (mt.n <= 0) return 0;
+    return (2 * (mt.K + 1) + kForceTerms - 1) / kForceTerms * kForceTerms;
+}
+
 int validate_lattice(const rlbm_lattice* lat) {
     if (!lat) return fail(RLBM_EINVAL, "lattice is NULL");
     if (lat->nx < 2 || lat->ny < 2 || lat->nx > 65536 || lat->ny > 65536)
@@ -97,7 +104,7 @@ int pitch_of(int nx) { return (nx + kTileW - 1) / kTileW * kTileW; }
 // force tables, mode tables).
 struct Layout {
     size_t ctl = 0, desc = 0, red = 0, tiles[2] = {0, 0}, gitems[2] = {0, 0}, total = 0;
-    struct Per { size_t buf0, buf1, twx, twy, g[4], modes, kptr; };
+    struct Per { size_t buf0, buf1, twx, twy, g[4], bas, modes, kptr; };
     std::vector<Per> per;
     int max_partials = 0;
 };
@@ -133,8 +140,13 @@ int compute_layout(int n_real, const rlbm_lattice* lats, int stencil, int storag
         P.buf1 = off; off = align_up(off + plane * Q * s);
         P.twx = off; off = align_up(off + cs * 2 * lats[r].nx);
         P.twy = off; off = align_up(off + cs * 2 * lats[r].ny);
-        const size_t g = (size_t)lats[r].ny * (mts[r].K + 1) * 4 + kTableSlack;
+        // force tables: FP64 [ny][K+1][4]; FP32 [ny][J][2] and the basis [nx][J]
+        const int J = force_terms(mts[r]);
+        const size_t g = storage == RLBM_F64 ? (size_t)lats[r].ny * (mts[r].K + 1) * 4 + kTableSlack
+                                             : (size_t)lats[r].ny * 2 * J + kTableSlack;
         for (int k = 0; k < 4; ++k) { P.g[k] = off; off = align_up(off + cs * g); }
+        P.bas = off;
+        if (storage != RLBM_F64) off = align_up(off + sizeof(float) * (size_t)lats[r].nx * J);
         P.modes = off; off = align_up(off + sizeof(int4) * mts[r].modes.size());
         P.kptr = off; off = align_up(off + sizeof(int) * mts[r].kptr.size());
     }
@@ -175,6 +187,7 @@ struct Engine {
     bool any_forced = false;
     int cus = 0;
     int dev = 0;                     // device the engine was created on
+    int maxJ = 0;                    // FP32 force terms per row, largest over the lattices
     Cfg cfg[2];                      // [0] one step per launch, [1] two steps per launch
     bool pairs = false;              // advance pairs of steps with cfg[1]
     bool kind_auto = true;           // until rlbm_set_kernel / rlbm_set_tile / autotune
@@ -196,12 +209,30 @@ struct Engine {
         graph_built_chunk = 0;
     }
 
+    // Dynamic LDS of a launch: the marching forms of FP32 and 16-bit storage
+    // keep their strip's force basis there (64 columns, 128 for the paired
+    // form, J terms each).
+    size_t lds_bytes(int kind) const {
+        if (storage == RLBM_F64 || !any_forced) return 0;
+        const size_t cols = kind == kKernelMarchPair ? 2 * kTileW
+                            : (kind == kKernelMarch || kind == kKernelMarch2) ? kTileW : 0;
+        return cols * (size_t)maxJ * sizeof(float);
+    }
+    // The marching forms hold at most kMaxMarchJ force terms per row in
+    // registers and LDS (forcing shells with |kx| <= 63).
+    static constexpr int kMaxMarchJ = 128;
+    bool kind_fits(int kind) const {
+        return kind == kKernelTile || kind == kKernelStaged || storage == RLBM_F64 ||
+               maxJ <= kMaxMarchJ;
+    }
+
     int occupancy(int kind, int th) const {
+        const size_t lds = lds_bytes(kind);
         switch (storage) {
-            case RLBM_F64: return occ_f64(kind, stencil, smode, any_forced, th);
-            case RLBM_F32: return occ_f32(kind, stencil, smode, any_forced, th);
-            case RLBM_F16S: return occ_f16s(kind, stencil, smode, any_forced, th);
-            default: return occ_bf16s(kind, stencil, smode, any_forced, th);
+            case RLBM_F64: return occ_f64(kind, stencil, smode, any_forced, th, lds);
+            case RLBM_F32: return occ_f32(kind, stencil, smode, any_forced, th, lds);
+            case RLBM_F16S: return occ_f16s(kind, stencil, smode, any_forced, th, lds);
+            default: return occ_bf16s(kind, stencil, smode, any_forced, th, lds);
         }
     }
 
@@ -230,8 +261,8 @@ struct Engine {
         c.th = 4;
         const long long waves = (long long)cus * occupancy(kKernelMarch, 4) * 4;
         const bool long_segments = wave_rows(kTileW) >= 8 * std::max(1LL, waves);
-        c.kind = (storage != RLBM_F64 && long_segments && smode != kStreamHalo2) ? kKernelMarch
-                                                                                : kKernelTile;
+        c.kind = (storage != RLBM_F64 && long_segments && smode != kStreamHalo2 &&
+                  kind_fits(kKernelMarch)) ? kKernelMarch : kKernelTile;
         c.seglen_req = 0;
         pairs = false;
         cfg[1].kind = kKernelMarch2;
@@ -267,7 +298,7 @@ struct Engine {
                 long long n = 0;
                 for (int r = 0; r < n_real; ++r)
                     n += (long long)((hdesc[r].nx + width - 1) / width) *
-                         ((hdesc[r].ny + sl - 1) / sl);
+                         (((hdesc[r].ny + sl - 1) / sl + 3) & ~3);
                 return n;
             };
             while (units(seg) > target && seg < 65536) ++seg;
@@ -283,6 +314,10 @@ struct Engine {
             w.tiles_x = (d.nx + width - 1) / width;
             w.seglen = c.seglen;
             w.tiles_y = (d.ny + w.seglen - 1) / w.seglen;
+            // the marching forms number the segments of a strip consecutively,
+            // padded to a multiple of the block's four wavefronts (which share
+            // the strip's force basis)
+            if (!tiled) w.tiles_y = (w.tiles_y + 3) & ~3;
             w.tile_begin = c.n_tiles;
             c.n_tiles += w.tiles_x * w.tiles_y;
             if (n_real > 1) map.insert(map.end(), (size_t)w.tiles_x * w.tiles_y, (uint16_t)r);
@@ -348,6 +383,7 @@ struct Engine {
         L.smode = smode;
         L.forced = any_forced;
         L.grid = c.grid;
+        L.lds = lds_bytes(c.kind);
         L.stream = s;
         return L;
     }
@@ -564,6 +600,9 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         d.twx = E.ws + P.twx;
         d.twy = E.ws + P.twy;
         for (int k = 0; k < 4; ++k) d.g[k] = E.ws + P.g[k];
+        d.bas = storage != RLBM_F64 ? (const float*)(E.ws + P.bas) : nullptr;
+        d.J = storage != RLBM_F64 ? force_terms(E.mts[r]) : 0;
+        E.maxJ = std::max(E.maxJ, d.J);
         d.modes = (const int4*)(E.ws + P.modes);
         d.kptr = (const int*)(E.ws + P.kptr);
         d.nx = lat.nx;
@@ -615,6 +654,25 @@ int engine_init(Engine& E, int n_real, const rlbm_lattice* lats, const double* t
         const auto& P = E.lay.per[r];
         if (int rc2 = upload_tw(P.twx, lats[r].nx)) return rc2;
         if (int rc2 = upload_tw(P.twy, lats[r].ny)) return rc2;
+        const int J = E.hdesc[r].J;
+        if (!f64 && J > 0) {
+            // FP32 force basis [nx][J]: term 2k = cos(2 pi k x / nx), 2k + 1 =
+            // sin(...), rounded from FP64 at the exactly reduced angle (k x mod
+            // nx); the terms past 2 K + 1 and the tables' padding terms are 0
+            const int nx = lats[r].nx, K = E.mts[r].K;
+            std::vector<float> bas((size_t)nx * J, 0.0f);
+            for (int x = 0; x < nx; ++x)
+                for (int k = 0; k <= K; ++k) {
+                    const double a = 2.0 * M_PI * (double)(((long long)k * x) % nx) / (double)nx;
+                    bas[(size_t)x * J + 2 * k] = (float)std::cos(a);
+                    bas[(size_t)x * J + 2 * k + 1] = (float)std::sin(a);
+                }
+            HIPCHK(hipMemcpyAsync(E.ws + P.bas, bas.data(), sizeof(float) * bas.size(),
+                                  hipMemcpyHostToDevice, E.stream));
+            const size_t gbytes = sizeof(float) * ((size_t)lats[r].ny * 2 * J + kTableSlack);
+            for (int k = 0; k < 4; ++k) HIPCHK(hipMemsetAsync(E.ws + P.g[k], 0, gbytes, E.stream));
+            HIPCHK(hipStreamSynchronize(E.stream));
+        }
         if (!E.mts[r].modes.empty()) {
             HIPCHK(hipMemcpyAsync(E.ws + P.modes, E.mts[r].modes.data(),
                                   sizeof(int4) * E.mts[r].modes.size(), hipMemcpyHostToDevice,
@@ -1148,6 +1206,8 @@ int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
         if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
         if (E.smode == kStreamHalo2)
             return fail(RLBM_EUNSUPPORTED, "the row-marching forms need cfl <= 1");
+        if (!E.kind_fits(kKernelMarchPair))
+            return fail(RLBM_EUNSUPPORTED, "the row-marching forms need forcing modes with |kx| <= 63");
         if (E.storage != RLBM_F16S && E.storage != RLBM_BF16S)
             return fail(RLBM_EUNSUPPORTED, "the paired marching form is for 16-bit storage");
         E.cfg[0].kind = kKernelMarchPair;
@@ -1157,6 +1217,8 @@ int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
         if (param < 0 || param > 65536) return fail(RLBM_EINVAL, "segment length must be in [0, 65536]");
         if (E.smode == kStreamHalo2)
             return fail(RLBM_EUNSUPPORTED, "the row-marching forms need cfl <= 1");
+        if (!E.kind_fits(kKernelMarch))
+            return fail(RLBM_EUNSUPPORTED, "the row-marching forms need forcing modes with |kx| <= 63");
         if (kind == RLBM_KERNEL_MARCH) {
             E.cfg[0].kind = kKernelMarch;
             E.cfg[0].seglen_req = param;
@@ -1245,6 +1307,8 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     for (const auto& c : cand) {
         if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
         if (c[0] == RLBM_KERNEL_MARCH_PAIRS && !bits16) continue;
+        if (c[0] != RLBM_KERNEL_TILE && c[0] != RLBM_KERNEL_STAGED && !E.kind_fits(kKernelMarch))
+            continue;
         if (c[0] == RLBM_KERNEL_MARCH2 && min_ny < 3) continue;
         const int a = auto_seg[c[0]];
         int param = c[1];

@@ -13,6 +13,7 @@ namespace rlbm {
 
 constexpr int kTileW = 64;            // sites per tile row = one wavefront
 constexpr int kTableSlack = 32;       // compute-type values after the last row of a force table
+constexpr int kForceTerms = 16;       // FP32 force terms are padded to a multiple of this
 
 // Work decomposition of one lattice for one launch configuration.
 struct WorkMap {
@@ -30,14 +31,20 @@ struct RealDesc {
     const void* twx;              // [nx][2] cos, sin of 2 pi x / nx (compute type)
     const void* twy;              // [ny][2] cos, sin of 2 pi y / ny (compute type)
     void* g[4];                   // force table of step s in g[s & 3]:
-                                  //   [ny][K+1][4] = Px, Qx, Py, Qy (compute type),
+                                  //   FP64: [ny][K+1][4] = Px, Qx, Py, Qy;
+                                  //   FP32: [ny][J][2], term 2k = (Px, Py),
+                                  //   2k + 1 = (-Qx, -Qy), zero past 2 K + 1;
                                   //   then kTableSlack values that are never used
+    const float* bas;             // FP32 forms: force basis [nx][J], term 2k =
+                                  //   cos(2 pi k x / nx), 2k + 1 = sin(...)
     const int4* modes;            // (kx, ky, m, 0) grouped by |kx|
     const int* kptr;              // K+2 offsets into modes
     int nx, ny;
     int pitch;                    // nx rounded up to 64; see pop_index for the layout
     WorkMap wm[2];                // [0]: one-step launches, [1]: two-step launches
     int K;                        // largest |kx| of the driven modes; -1 unforced
+    int J;                        // FP32 forms: force terms per row, 2 (K + 1)
+                                  //   rounded up to kForceTerms (0 unforced)
     int n_modes;
     int realization;              // Philox counter word 2
     int tau_mode;                 // RLBM_TAU_CONSTANT or RLBM_TAU_ETA_S
@@ -102,6 +109,7 @@ struct StepLaunch {
     int smode;                    // kStreamGeneral / kStreamUnit / kStreamHalo2
     bool forced;
     int grid;                     // persistent blocks
+    size_t lds = 0;               // dynamic LDS bytes per block
     hipStream_t stream;
     hipEvent_t ev_start = nullptr;  // optional: kernel start/stop timestamps
     hipEvent_t ev_stop = nullptr;
@@ -113,10 +121,10 @@ hipError_t launch_step_f32(const StepLaunch& L);
 hipError_t launch_step_f16s(const StepLaunch& L);
 hipError_t launch_step_bf16s(const StepLaunch& L);
 // Resident blocks per CU of a step-kernel configuration (occupancy query).
-int occ_f64(int kind, int stencil, int smode, bool forced, int th);
-int occ_f32(int kind, int stencil, int smode, bool forced, int th);
-int occ_f16s(int kind, int stencil, int smode, bool forced, int th);
-int occ_bf16s(int kind, int stencil, int smode, bool forced, int th);
+int occ_f64(int kind, int stencil, int smode, bool forced, int th, size_t lds);
+int occ_f32(int kind, int stencil, int smode, bool forced, int th, size_t lds);
+int occ_f16s(int kind, int stencil, int smode, bool forced, int th, size_t lds);
+int occ_bf16s(int kind, int stencil, int smode, bool forced, int th, size_t lds);
 
 // Force table of the current step (kernels_aux.hip), for initial states.
 hipError_t launch_force_table(const StepArgs& a, bool fp32, hipStream_t s);

@@ -55,6 +55,125 @@ __device__ __forceinline__ void build_force_tables(const StepArgs& A, int64_t st
     }
 }
 
+// ---------------------------------------------------------------------------
+// Stirring force of the FP32 forms (force_chunk in site.hpp): the marching
+// forms keep the force basis of their strip in LDS, [J/4][W][4] floats (the
+// float4 at g W + col holds terms 4 g .. 4 g + 3 of strip column col), shared
+// by the four wavefronts of a block, which march down consecutive segments of
+// one strip.  Coefficient registers: kCoefRegs chunks of 16 terms (2 K + 2 <=
+// 16 kCoefRegs, i.e. K <= 63) are loaded one row iteration ahead of their
+// use; longer sums load the rest where they are used.
+// ---------------------------------------------------------------------------
+extern __shared__ v4f lds_basis[];
+constexpr int kCoefRegs = 8;
+
+// The basis of columns colx(0 .. W-1), block-cooperative.
+template <class ColX>
+__device__ __forceinline__ void stage_basis(const float* bas, int J, int W, ColX&& colx) {
+    const int tid = (int)(threadIdx.y * blockDim.x + threadIdx.x);
+    const int nt = (int)(blockDim.x * blockDim.y);
+    const int G = J >> 2;
+    const gp<const v4f> b4 = (gp<const v4f>)bas;
+    for (int f = tid; f < G * W; f += nt) {
+        const int g = f / W, col = f - g * W;
+        lds_basis[f] = b4[(size_t)colx(col) * G + g];
+    }
+}
+
+// Coefficient registers of the rows rowA (outputs 0, 1) and rowB (2, 3).
+__device__ __forceinline__ void load_coefs(float (&cf)[kCoefRegs], const float* rowA,
+                                           const float* rowB, int nch, const ForceLane& fl) {
+    const gp<const float> row = (gp<const float>)(fl.hi ? rowB : rowA) + fl.off;
+#pragma unroll
+    for (int c = 0; c < kCoefRegs; ++c)
+        if (c < nch) cf[c] = row[kForceChunk * 2 * c];
+}
+
+// The four sums of this lane's strip column col (basis in LDS, W columns).
+__device__ __forceinline__ v4f force_sum_lds(const float (&cf)[kCoefRegs], const float* rowA,
+                                             const float* rowB, int nch, int col, int W,
+                                             const ForceLane& fl) {
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    auto basis = [&](int c, v4f (&b)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = lds_basis[(4 * c + i) * W + col];
+    };
+#pragma unroll
+    for (int c = 0; c < kCoefRegs; ++c) {
+        if (c < nch) {
+            v4f b[4];
+            basis(c, b);
+            acc = force_chunk(acc, cf[c], b);
+        }
+    }
+    if (nch > kCoefRegs) {
+        const gp<const float> row = (gp<const float>)(fl.hi ? rowB : rowA) + fl.off;
+        for (int c = kCoefRegs; c < nch; ++c) {
+            v4f b[4];
+            basis(c, b);
+            acc = force_chunk(acc, row[kForceChunk * 2 * c], b);
+        }
+    }
+    return acc;
+}
+
+// The same sums by FP32 fused multiply-adds on the vector ALU, in the same
+// term order (each MFMA above is one fused multiply-add per output, so the
+// results are bitwise those of the matrix-core sums): the coefficients of one
+// table row as constant memory (scalar loads, SGPRs), the basis of the nc
+// strip columns cols[0 .. nc-1] from LDS; F[2 i], F[2 i + 1] = (Fx, Fy) of
+// column cols[i].  For the one-step marching forms, whose wavefronts issue far
+// more vector-ALU work per force sum than the two-step form.
+template <int NC>
+__device__ __forceinline__ void force_sum_valu(const float* row, int J, const int (&cols)[NC],
+                                               int W, float (&F)[2 * NC]) {
+    const kp<const float> r = (kp<const float>)row;
+#pragma unroll
+    for (int i = 0; i < 2 * NC; ++i) F[i] = 0.f;
+    for (int c = 0; c < J / kForceChunk; ++c) {
+        float cv[2 * kForceChunk];
+#pragma unroll
+        for (int i = 0; i < 2 * kForceChunk; ++i) cv[i] = r[2 * kForceChunk * c + i];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            v4f b[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) b[k] = lds_basis[(4 * c + g) * W + cols[k]];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = 4 * g + i;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    F[2 * k] = fmaf(cv[2 * t], b[k][i], F[2 * k]);
+                    F[2 * k + 1] = fmaf(cv[2 * t + 1], b[k][i], F[2 * k + 1]);
+                }
+            }
+        }
+    }
+}
+
+// Work items of the marching forms: a block's four wavefronts take four
+// consecutive segments of one strip (they share the strip's force basis);
+// consecutive blocks take the next strip of the same rows, so the wavefronts
+// running at a time spread over the columns of a band of rows (as the rows of
+// one strip, 64 columns apart in the brick layout, would all map to the same
+// memory channels).  The segment count of a strip is padded to a multiple of
+// 4; a padding item has no rows.
+struct MarchItem {
+    int strip, seg, ya, yb;
+    bool rows;
+    __device__ void decode(int local, int strips, int ny, int seglen) {
+        const int segs = (ny + seglen - 1) / seglen;
+        const int grp = local >> 2;
+        const int band = grp / strips;
+        strip = grp - band * strips;
+        seg = 4 * band + (local & 3);
+        rows = seg < segs;
+        ya = seg * seglen;
+        yb = min(ny, ya + seglen);
+    }
+};
+
 template <class S, class St, int SM, bool FORCED>
 __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     using T = typename S::T;
@@ -62,10 +181,14 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
     constexpr int D = St::D;
     constexpr bool F64 = std::is_same<T, double>::value;
 
+    constexpr bool MF = FORCED && !F64;       // FP32 force sums on the matrix cores
+
     const int64_t step = A.d_step[0] + A.step_off;
     const int par = (int)((A.d_step[1] + A.launch_off) & 1);
     const int lx = threadIdx.x;
     const int ly = threadIdx.y;
+    ForceLane fl;
+    fl.init(lx);
 
     // XCD-aware persistent schedule: XCD x = b mod 8 owns tiles
     // [x * chunk, (x + 1) * chunk); its nb blocks stride through them.
@@ -82,7 +205,8 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
 
     // per-lattice context, reloaded when the lattice changes (ensembles)
     int cur_r = -1;
-    int nx = 0, ny = 0, tiles_x = 1, tile_begin = 0, K = -1;
+    int nx = 0, ny = 0, tiles_x = 1, tile_begin = 0, K = -1, J = 0;
+    const float* bas = nullptr;
     int dq = 0, dr = 0;                      // nb = dq * tiles_x + dr
     long long rowq_bytes = 0;
     const char* src = nullptr;
@@ -123,6 +247,10 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
                 K = uni(Dsc.K);
                 twp = uni((const T*)Dsc.twx);
                 gtab = uni((const T*)Dsc.g[step & 3]);
+                if constexpr (MF) {
+                    J = uni(Dsc.J);
+                    bas = uni(Dsc.bas);
+                }
             }
             dq = nb / tiles_x;
             dr = nb - dq * tiles_x;
@@ -142,7 +270,20 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
         t_prev = t;
         const int x = txi * kTileW + lx;
         const int y = uni(tyi * A.th + ly);          // one tile row per wavefront
-        if (x >= nx || y >= ny) continue;
+        if (y >= ny) continue;
+        // FP32 force sum with every lane of the wavefront (lanes past the
+        // lattice take its last column)
+        T Fx = 0, Fy = 0;
+        if constexpr (MF) {
+            if (K >= 0) {
+                const float* row = (const float*)gtab + (size_t)y * 2 * J;
+                const v4f acc = force_sum_global(row, row, bas + (size_t)min(x, nx - 1) * J,
+                                                 J / kForceChunk, fl);
+                Fx = acc[0];
+                Fy = acc[1];
+            }
+        }
+        if (x >= nx) continue;
 
         // (b) stream
         T f[St::Q];
@@ -171,15 +312,13 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
         }
 
         const SiteCtx<T> sctx{ginv, dt, K, gtab, eta_s};
-        T c1 = 0, s1 = 0;
-        if constexpr (FORCED) {
+        if constexpr (FORCED && F64) {
             if (K >= 0) {
                 const gp<const T> twx = (gp<const T>)twp;
-                c1 = twx[2 * x];
-                s1 = twx[2 * x + 1];
+                force_cheb64(sctx, twx[2 * x], twx[2 * x + 1], y, Fx, Fy);
             }
         }
-        update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), col_bytes<raw>(x, St::Q),
+        update_site<S, St, FORCED>(f, sctx, Fx, Fy, (gp<char>)(dst + y * rowq_bytes), col_bytes<raw>(x, St::Q),
                                    A.d_flag);
     }
 
@@ -265,8 +404,11 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
 
     const int64_t step = A.d_step[0] + A.step_off;
     const int par = (int)((A.d_step[1] + A.launch_off) & 1);
+    constexpr bool MF = FORCED && !F64;       // FP32 force sums on the matrix cores
     const int lx = threadIdx.x;
     const int w = uni((int)threadIdx.y);
+    ForceLane fl;
+    fl.init(lx);
 
     // XCD-aware persistent schedule, as in step_kernel
     const int G = A.tile_blocks;
@@ -296,7 +438,8 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
     });
 
     int cur_r = -1;
-    int nx = 0, ny = 0, tiles_x = 1, tile_begin = 0, K = -1;
+    int nx = 0, ny = 0, tiles_x = 1, tile_begin = 0, K = -1, J = 0;
+    const float* bas = nullptr;
     long long rowq_bytes = 0;
     const char* src = nullptr;
     char* dst = nullptr;
@@ -331,6 +474,10 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
                 K = uni(Dsc.K);
                 twp = uni((const T*)Dsc.twx);
                 gtab = uni((const T*)Dsc.g[step & 3]);
+                if constexpr (MF) {
+                    J = uni(Dsc.J);
+                    bas = uni(Dsc.bas);
+                }
             }
             cur_r = r;
         }
@@ -373,6 +520,18 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
         __syncthreads();
 
         const int y = y0 + w;
+        // FP32 force sum with every lane of the wavefront (lanes past the
+        // lattice take its last column)
+        T Fx = 0, Fy = 0;
+        if constexpr (MF) {
+            if (K >= 0 && y < ny) {
+                const float* row = (const float*)gtab + (size_t)y * 2 * J;
+                const v4f acc = force_sum_global(row, row, bas + (size_t)min(x0 + lx, nx - 1) * J,
+                                                 J / kForceChunk, fl);
+                Fx = acc[0];
+                Fy = acc[1];
+            }
+        }
         if (lx <= R && y < ny) {
             T f[Q];
             stream_interp<St, SM>(
@@ -381,15 +540,13 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
                 },
                 W, f);
             const SiteCtx<T> sctx{ginv, dt, K, gtab, eta_s};
-            T c1 = 0, s1 = 0;
-            if constexpr (FORCED) {
+            if constexpr (FORCED && F64) {
                 if (K >= 0) {
                     const gp<const T> twx = (gp<const T>)twp;
-                    c1 = twx[2 * (x0 + lx)];
-                    s1 = twx[2 * (x0 + lx) + 1];
+                    force_cheb64(sctx, twx[2 * (x0 + lx)], twx[2 * (x0 + lx) + 1], y, Fx, Fy);
                 }
             }
-            update_site<S, St, FORCED>(f, sctx, c1, s1, y, (gp<char>)(dst + y * rowq_bytes), colb,
+            update_site<S, St, FORCED>(f, sctx, Fx, Fy, (gp<char>)(dst + y * rowq_bytes), colb,
                                        A.d_flag);
         }
         __syncthreads();                     // before the next tile overwrites LDS
@@ -465,18 +622,6 @@ struct MarchMap {
 };
 
 template <class T>
-__device__ __forceinline__ T lane_from(T v, int addr_bytes) {
-    if constexpr (std::is_same<T, double>::value) {
-        const long long b = __double_as_longlong(v);
-        const int lo = __builtin_amdgcn_ds_bpermute(addr_bytes, (int)(unsigned)(b & 0xffffffffu));
-        const int hi = __builtin_amdgcn_ds_bpermute(addr_bytes, (int)(b >> 32));
-        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-    } else {
-        return __int_as_float(__builtin_amdgcn_ds_bpermute(addr_bytes, __float_as_int(v)));
-    }
-}
-
-template <class T>
 __device__ __forceinline__ T read_lane(T v, int lane) {
     if constexpr (std::is_same<T, double>::value) {
         const long long b = __double_as_longlong(v);
@@ -485,6 +630,26 @@ __device__ __forceinline__ T read_lane(T v, int lane) {
         return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
     } else {
         return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    }
+}
+
+// v from the lane one below (C > 0) or one above (C < 0) by a DPP wave shift
+// (a vector-ALU move instead of an LDS permute); the lane that has no source
+// lane (0 or 63) takes edge.
+template <int C, class T>
+__device__ __forceinline__ T lane_shift(T v, T edge) {
+    constexpr int ctrl = C > 0 ? 0x138 : 0x130;        // wave_shr:1 / wave_shl:1
+    if constexpr (std::is_same<T, double>::value) {
+        const long long b = __double_as_longlong(v), e = __double_as_longlong(edge);
+        const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)(e & 0xffffffffu),
+                                                   (int)(unsigned)(b & 0xffffffffu), ctrl, 0xf, 0xf,
+                                                   false);
+        const int hi = __builtin_amdgcn_update_dpp((int)(e >> 32), (int)(b >> 32), ctrl, 0xf, 0xf,
+                                                   false);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v),
+                                                          ctrl, 0xf, 0xf, false));
     }
 }
 
@@ -503,6 +668,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
     constexpr int Q = St::Q;
     constexpr int NH = M::nH();
     constexpr bool F64 = std::is_same<T, double>::value;
+    constexpr bool MF = FORCED && !F64;       // FP32 force sums on the matrix cores
 
     const int64_t step = A.d_step[0] + A.step_off;
     const int par = (int)((A.d_step[1] + A.launch_off) & 1);
@@ -519,23 +685,34 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
     const int chunk = (n_groups + 7) >> 3;
     const int g_end = min(n_groups, (xcd + 1) * chunk);
 
+    // The loop over groups is uniform over the block (the basis barriers).
     for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
         const int u = grp * 4 + wv;
-        if (u >= A.n_tiles) continue;
         const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
-        const int strips = uni(Dsc.wm[A.map].tiles_x);
-        const int seglen = uni(Dsc.wm[A.map].seglen);
-        const int local = u - uni(Dsc.wm[A.map].tile_begin);
-        const int seg = local / strips;
-        const int strip = local - seg * strips;
-        const int ya = seg * seglen;
-        const int yb = min(ny, ya + seglen);
-        const int x0 = strip * kTileW;
+        MarchItem it;
+        it.decode(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
+                  uni(Dsc.wm[A.map].seglen));
+        const int ya = it.ya, yb = it.yb;
+        const int x0 = it.strip * kTileW;
         const int R = min(kTileW - 1, nx - 1 - x0);      // last active lane
         const int x = x0 + lane;
         const bool active = lane <= R;
+        int K = -1, J = 0;
+        if constexpr (FORCED) {
+            K = uni(Dsc.K);
+            if constexpr (MF) J = uni(Dsc.J);
+        }
+        if constexpr (MF) {
+            // this strip's force basis, shared by the block's four wavefronts
+            // (columns past the lattice take its last column's)
+            __syncthreads();
+            if (K >= 0)
+                stage_basis(uni(Dsc.bas), J, kTileW, [&](int col) { return min(x0 + col, nx - 1); });
+            __syncthreads();
+        }
+        if (!it.rows) continue;
         constexpr long long plane_bytes = kTileW * sizeof(raw);
         const long long rowq = (long long)uni(Dsc.pitch) * Q * (long long)sizeof(raw);
         const char* src = (const char*)uni(Dsc.buf[par]);
@@ -551,19 +728,24 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
             sctx.ginv = uni(Dsc.inv_tauf);
             sctx.dt = uni(Dsc.dtf);
         }
-        sctx.K = -1;
+        sctx.K = K;
         sctx.eta_s = uni(Dsc.tau_mode);
         sctx.gtab = nullptr;
         T c1 = 0, s1 = 0;
         if constexpr (FORCED) {
-            sctx.K = uni(Dsc.K);
             sctx.gtab = uni((const T*)Dsc.g[step & 3]);
-            if (sctx.K >= 0 && active) {
-                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
-                c1 = twx[2 * x];
-                s1 = twx[2 * x + 1];
+            if constexpr (F64) {
+                if (K >= 0 && active) {
+                    const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
+                    c1 = twx[2 * x];
+                    s1 = twx[2 * x + 1];
+                }
             }
         }
+        // FP32 forms: force sums on the vector ALU (basis in LDS)
+        const float* gsf = nullptr;
+        if constexpr (MF) gsf = (const float*)sctx.gtab;
+        const int cols[1] = {lane};
         const uint32_t colb = col_bytes<raw>(x, Q);
         auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
         auto ld = [&](int q, int yy) -> T {
@@ -631,26 +813,43 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
                     if constexpr (UNIT && n == 1) f[q] = vert;
                     else f[q] = lerp(own, vert, W.a[n - 1]);
                 } else {
-                    // x-neighbour upstream: lane - 1 for c_x > 0, lane + 1 for c_x < 0
+                    // x-neighbour upstream: lane - 1 for c_x > 0, lane + 1 for c_x < 0,
+                    // by a wave shift; the edge lane takes the halo column -- lane 0,
+                    // or for c_x < 0 the last active lane R, through lane R + 1 when
+                    // R < 63 (a ragged last strip) and as the shift's edge value
+                    // when R = 63
                     constexpr int H = M::hidx(q);
-                    const int addr = (lane - d.cx) * 4;
-                    const int fix = d.cx > 0 ? 0 : R;
+                    auto shifted = [&](T v, T h) -> T {
+                        if constexpr (d.cx > 0) return lane_shift<1>(v, h);
+                        else return lane_shift<-1>(lane == R + 1 ? h : v, h);
+                    };
                     const T h_own = read_lane(d.cy < 0 ? hp : hc, H);   // halo, row y
-                    const T own_nb = write_lane(lane_from(own, addr), h_own, fix);
+                    const T own_nb = shifted(own, h_own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = own_nb;
                         else f[q] = lerp(own, own_nb, W.a[n - 1]);
                     } else {
                         // halo of the upstream row: y-1 (in hp) or y+1 (in hc)
                         const T h_vert = read_lane(d.cy > 0 ? hp : hc, H);
-                        const T vert_nb = write_lane(lane_from(vert, addr), h_vert, fix);
+                        const T vert_nb = shifted(vert, h_vert);
                         f[q] = fma(W.w11[n - 1], vert_nb,
                                    fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
                     }
                 }
             });
+            T Fx = 0, Fy = 0;
+            if constexpr (MF) {
+                if (K >= 0) {
+                    float F[2];
+                    force_sum_valu(gsf + (size_t)y * 2 * J, J, cols, kTileW, F);
+                    Fx = F[0];
+                    Fy = F[1];
+                }
+            } else if constexpr (FORCED) {
+                force_cheb64(sctx, c1, s1, y, Fx, Fy);
+            }
             if (active)
-                update_site<S, St, FORCED, true>(f, sctx, c1, s1, y,
+                update_site<S, St, FORCED, true>(f, sctx, Fx, Fy,
                                                  (gp<char>)(dst + (long long)y * rowq), colb,
                                                  A.d_flag);
             // roll the window
@@ -730,21 +929,30 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
         return (uint32_t)__builtin_amdgcn_ds_bpermute(addr_bytes, (int)u);
     };
 
+    // The loop over groups is uniform over the block (the basis barriers).
     for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
         const int u = grp * 4 + wv;
-        if (u >= A.n_tiles) continue;
         const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
         const int pitch = uni(Dsc.pitch);
-        const int strips = uni(Dsc.wm[A.map].tiles_x);
-        const int seglen = uni(Dsc.wm[A.map].seglen);
-        const int local = u - uni(Dsc.wm[A.map].tile_begin);
-        const int seg = local / strips;
-        const int strip = local - seg * strips;
-        const int ya = seg * seglen;
-        const int yb = min(ny, ya + seglen);
-        const int x0 = strip * kW;
+        MarchItem it;
+        it.decode(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
+                  uni(Dsc.wm[A.map].seglen));
+        const int ya = it.ya, yb = it.yb;
+        const int x0 = it.strip * kW;
+        int K = -1, J = 0;
+        if constexpr (FORCED) {
+            K = uni(Dsc.K);
+            J = uni(Dsc.J);
+            // this strip's force basis (128 columns), shared by the block's
+            // four wavefronts; columns past the lattice take its last column's
+            __syncthreads();
+            if (K >= 0)
+                stage_basis(uni(Dsc.bas), J, kW, [&](int col) { return min(x0 + col, nx - 1); });
+            __syncthreads();
+        }
+        if (!it.rows) continue;
         const int Rc = min(kW - 1, nx - 1 - x0);        // last column of the strip
         const int Lr = Rc >> 1;                         // lane of the last column
         const bool last_is_b = (Rc & 1) != 0;
@@ -760,19 +968,13 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
         W.set(uni(Dsc.af[0]), uni(Dsc.af[1]), uni(Dsc.af[2]));
         sctx.ginv = uni(Dsc.inv_tauf);
         sctx.dt = uni(Dsc.dtf);
-        sctx.K = -1;
+        sctx.K = K;
         sctx.eta_s = uni(Dsc.tau_mode);
         sctx.gtab = nullptr;
-        T c1a = 0, s1a = 0, c1b = 0, s1b = 0;
-        if constexpr (FORCED) {
-            sctx.K = uni(Dsc.K);
-            sctx.gtab = uni((const T*)Dsc.g[step & 3]);
-            if (sctx.K >= 0) {
-                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
-                if (activeA) { c1a = twx[2 * xa]; s1a = twx[2 * xa + 1]; }
-                if (activeB) { c1b = twx[2 * xa + 2]; s1b = twx[2 * xa + 3]; }
-            }
-        }
+        if constexpr (FORCED) sctx.gtab = uni((const T*)Dsc.g[step & 3]);
+        // force sums of columns A and B on the vector ALU (basis in LDS)
+        const float* gsf = (const float*)sctx.gtab;
+        const int cols[2] = {2 * lane, 2 * lane + 1};
         // the pair's byte offset in a row; lanes past the padded row read its last pair
         const uint32_t colb = col_bytes<raw>(min(xa, pitch - 2), Q);
         auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
@@ -844,6 +1046,10 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
             // (b)-(e) column A, then column B: one site's streamed populations
             // are live at a time.  The lane exchanges run on every lane (the
             // permutes sit outside the activity branches).
+            float FAB[4] = {0.f, 0.f, 0.f, 0.f};  // (Fx, Fy) of column A, of column B
+            if constexpr (FORCED) {
+                if (K >= 0) force_sum_valu(gsf + (size_t)y * 2 * J, J, cols, kW, FAB);
+            }
             T f[Q];
             uint32_t outp[Q];                     // the new pairs: A low, B high
             sfor<0, Q>([&](auto iq) {
@@ -881,7 +1087,7 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
             });
             if (activeA)
                 update_site_to<S, St, FORCED>(
-                    f, sctx, c1a, s1a, y,
+                    f, sctx, FAB[0], FAB[1],
                     [&](auto qc, raw r) { outp[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
                     A.d_flag);
             // column B converts the window's halves anew: values kept from column
@@ -925,7 +1131,7 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
             });
             if (activeB)
                 update_site_to<S, St, FORCED>(
-                    f, sctx, c1b, s1b, y,
+                    f, sctx, FAB[2], FAB[3],
                     [&](auto qc, raw r) {
                         constexpr int q = decltype(qc)::value;
                         outp[q] = (outp[q] & 0xffffu) | ((uint32_t)__builtin_bit_cast(uint16_t, r) << 16);
@@ -992,12 +1198,15 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
     constexpr int Q = St::Q;
     constexpr int NH = M::nH();
     constexpr bool F64 = std::is_same<T, double>::value;
+    constexpr bool MF = FORCED && !F64;       // FP32 force sums on the matrix cores
     constexpr int kOut = kTileW - 2;          // output columns per strip
 
     const int64_t step = A.d_step[0] + A.step_off;
     const int par = (int)((A.d_step[1] + A.launch_off) & 1);
     const int lane = threadIdx.x;
     const int wv = uni((int)threadIdx.y);
+    ForceLane fl;
+    fl.init(lane);
 
     const int G = A.tile_blocks;
     const int b = blockIdx.x;
@@ -1007,23 +1216,33 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
     const int chunk = (n_groups + 7) >> 3;
     const int g_end = min(n_groups, (xcd + 1) * chunk);
 
+    // The loop over groups is uniform over the block (the basis barriers).
     for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
         const int u = grp * 4 + wv;
-        if (u >= A.n_tiles) continue;
         const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
-        const int strips = uni(Dsc.wm[A.map].tiles_x);
-        const int seglen = uni(Dsc.wm[A.map].seglen);
-        const int local = u - uni(Dsc.wm[A.map].tile_begin);
-        const int seg = local / strips;
-        const int strip = local - seg * strips;
-        const int ya = seg * seglen;
-        const int yb = min(ny, ya + seglen);
-        const int x0 = strip * kOut;
+        MarchItem it;
+        it.decode(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
+                  uni(Dsc.wm[A.map].seglen));
+        const int ya = it.ya, yb = it.yb;
+        const int x0 = it.strip * kOut;
         auto wrapx = [&](int v) { v %= nx; return v < 0 ? v + nx : v; };
         const int xl = wrapx(x0 - 1 + lane);     // column of this lane (both steps)
         const bool out_lane = lane >= 1 && lane <= kOut && x0 + lane - 1 < nx;
+        int K = -1, J = 0;
+        if constexpr (FORCED) {
+            K = uni(Dsc.K);
+            if constexpr (MF) J = uni(Dsc.J);
+        }
+        if constexpr (MF) {
+            // this strip's force basis, shared by the block's four wavefronts
+            __syncthreads();                      // the previous strip's readers are done
+            if (K >= 0)
+                stage_basis(uni(Dsc.bas), J, kTileW, [&](int col) { return wrapx(x0 - 1 + col); });
+            __syncthreads();
+        }
+        if (!it.rows) continue;
         constexpr long long plane_bytes = kTileW * sizeof(raw);
         const long long rowq = (long long)uni(Dsc.pitch) * Q * (long long)sizeof(raw);
         const char* src = (const char*)uni(Dsc.buf[par]);
@@ -1039,17 +1258,18 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             c0.ginv = uni(Dsc.inv_tauf);
             c0.dt = uni(Dsc.dtf);
         }
-        c0.K = -1;
+        c0.K = K;
         c0.eta_s = uni(Dsc.tau_mode);
         c0.gtab = nullptr;
         T cs = 0, sn = 0;
         if constexpr (FORCED) {
-            c0.K = uni(Dsc.K);
             c0.gtab = uni((const T*)Dsc.g[step & 3]);
-            if (c0.K >= 0) {
-                const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
-                cs = twx[2 * xl];
-                sn = twx[2 * xl + 1];
+            if constexpr (F64) {
+                if (K >= 0) {
+                    const gp<const T> twx = (gp<const T>)uni((const T*)Dsc.twx);
+                    cs = twx[2 * xl];
+                    sn = twx[2 * xl + 1];
+                }
             }
         }
         c1x = c0;
@@ -1091,6 +1311,26 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         // at row rr into registers: the stores are followed by a whole
         // site update before the next row's loads are needed.
         const int r0 = ya - 1, r1 = yb;
+        // FP32 forms: the forces of iteration rr -- step s at row rr (outputs
+        // 0, 1) and step s + 1 at row rr - 2 (outputs 2, 3) -- are summed at
+        // the end of iteration rr - 1, from coefficients loaded at its start
+        const int nch = J / kForceChunk;
+        const float* gs0 = nullptr;
+        const float* gs1 = nullptr;
+        if constexpr (MF) {
+            gs0 = (const float*)c0.gtab;
+            gs1 = (const float*)c1x.gtab;
+        }
+        auto rowA = [&](int rr) { return gs0 + (size_t)wrap(min(rr, r1)) * 2 * J; };
+        auto rowB = [&](int rr) { return gs1 + (size_t)max(ya, min(rr - 2, yb - 1)) * 2 * J; };
+        v4f Fsum = {0.f, 0.f, 0.f, 0.f};
+        float cf[kCoefRegs];
+        if constexpr (MF) {
+            if (K >= 0) {
+                load_coefs(cf, rowA(r0), rowB(r0), nch, fl);
+                Fsum = force_sum_lds(cf, rowA(r0), rowB(r0), nch, lane, kTileW, fl);
+            }
+        }
         T cur[Q], up[M::nU], dn[M::nD];           // input rows rr, rr - 1, rr + 1
         T nxt[Q];                                 // in flight: rr + 1 (c_y >= 0), rr + 2 (c_y < 0)
         T sa[M::nU], sb[Q], sp[Q];                // step-s rows rr - 3 (c_y > 0), rr - 2, rr - 1
@@ -1106,6 +1346,9 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         T hn = gather(r0 + 1);
 
         for (int rr = r0; rr <= r1 + 1; ++rr) {
+            if constexpr (MF) {
+                if (K >= 0) load_coefs(cf, rowA(rr + 1), rowB(rr + 1), nch, fl);
+            }
             // step s + 1 at row rr - 2 from step-s rows rr - 3, rr - 2, rr - 1
             if (rr >= ya + 2) {
                 T g[Q];
@@ -1123,20 +1366,27 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                         if constexpr (UNIT && n == 1) g[q] = vert;
                         else g[q] = lerp(own, vert, W.a[n - 1]);
                     } else {
-                        const int addr = (lane - d.cx) * 4;
-                        const T own_nb = lane_from(own, addr);
+                        // lanes 1 .. 62 need no halo (edge lanes are not stored)
+                        const T own_nb = lane_shift<d.cx>(own, own);
                         if constexpr (d.cy == 0) {
                             if constexpr (UNIT && n == 1) g[q] = own_nb;
                             else g[q] = lerp(own, own_nb, W.a[n - 1]);
                         } else {
-                            const T vert_nb = lane_from(vert, addr);
+                            const T vert_nb = lane_shift<d.cx>(vert, vert);
                             g[q] = fma(W.w11[n - 1], vert_nb,
                                        fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
                         }
                     }
                 });
+                T Fx = 0, Fy = 0;
+                if constexpr (MF) {
+                    Fx = Fsum[2];
+                    Fy = Fsum[3];
+                } else if constexpr (FORCED) {
+                    force_cheb64(c1x, cs, sn, rr - 2, Fx, Fy);
+                }
                 if (out_lane)
-                    update_site<S, St, FORCED>(g, c1x, cs, sn, rr - 2,
+                    update_site<S, St, FORCED>(g, c1x, Fx, Fy,
                                                (gp<char>)(dst + (long long)(rr - 2) * rowq), colb,
                                                A.d_flag);
             }
@@ -1157,17 +1407,16 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                     if constexpr (UNIT && n == 1) f[q] = vert;
                     else f[q] = lerp(own, vert, W.a[n - 1]);
                 } else {
+                    // the edge lane (0 or 63) takes the strip's halo column
                     constexpr int H = M::hidx(q);
-                    const int addr = (lane - d.cx) * 4;
-                    const int fix = d.cx > 0 ? 0 : kTileW - 1;
                     const T h_own = read_lane(d.cy < 0 ? hp : hc, H);
-                    const T own_nb = write_lane(lane_from(own, addr), h_own, fix);
+                    const T own_nb = lane_shift<d.cx>(own, h_own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = own_nb;
                         else f[q] = lerp(own, own_nb, W.a[n - 1]);
                     } else {
                         const T h_vert = read_lane(d.cy > 0 ? hp : hc, H);
-                        const T vert_nb = write_lane(lane_from(vert, addr), h_vert, fix);
+                        const T vert_nb = lane_shift<d.cx>(vert, h_vert);
                         f[q] = fma(W.w11[n - 1], vert_nb,
                                    fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
                     }
@@ -1196,9 +1445,16 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             hp = hc;
             hc = hn;
             hn = gather(min(rr + 2, r1));
+            T Fx = 0, Fy = 0;
+            if constexpr (MF) {
+                Fx = Fsum[0];
+                Fy = Fsum[1];
+            } else if constexpr (FORCED) {
+                force_cheb64(c0, cs, sn, wrap(rr), Fx, Fy);
+            }
             T fn[Q];
             update_site_to<S, St, FORCED>(
-                f, c0, cs, sn, wrap(rr),
+                f, c0, Fx, Fy,
                 [&](auto qc, raw r) {              // the value a one-step launch stores
                     fn[decltype(qc)::value] = (T)S::ld(&r);
                 },
@@ -1210,6 +1466,10 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
                 sb[q] = sp[q];
                 sp[q] = fn[q];
             });
+            // the forces of the next iteration
+            if constexpr (MF) {
+                if (K >= 0) Fsum = force_sum_lds(cf, rowA(rr + 1), rowB(rr + 1), nch, lane, kTileW, fl);
+            }
         }
     }
 
@@ -1277,16 +1537,16 @@ hipError_t RLBM_LAUNCH_NAME(const StepLaunch& L) {
     StepArgs a = L.args;
     void* params[] = {&a};
     if (L.ev_start)
-        return hipExtLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, 0, L.stream,
+        return hipExtLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, L.lds, L.stream,
                                   L.ev_start, L.ev_stop, 0);
-    return hipLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, 0, L.stream);
+    return hipLaunchKernel(k, dim3(L.grid), dim3(kTileW, L.args.th), params, L.lds, L.stream);
 }
 
-int RLBM_OCC_NAME(int kind, int stencil, int smode, bool forced, int th) {
+int RLBM_OCC_NAME(int kind, int stencil, int smode, bool forced, int th, size_t lds) {
     int blocks = 0;
     const void* k = select_kernel(kind, stencil, smode, forced);
     if (!k) return 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kTileW * th, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kTileW * th, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }

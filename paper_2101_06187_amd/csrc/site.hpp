@@ -408,16 +408,137 @@ struct SiteCtx {
     int eta_s;             // 1: relaxation time tau(eps) = tau eps^(-1/4) (constant eta/s)
 };
 
+// ---------------------------------------------------------------------------
+// Force field at a site, FP64 path: F_c(x, y) = sum_k cos(k a) P_c(k, y) -
+// sin(k a) Q_c(k, y), a = 2 pi x / nx, from the FP64 force table
+// [ny][K+1][4] = (Px, Qx, Py, Qy), cos/sin(k a) by the Chebyshev recurrence
+// from (c1, s1) = (cos, sin)(a).  The table row of a wave's lattice row is the
+// same for all its lanes and was written by an earlier launch (a launch only
+// writes the tables of later steps), so it is read as constant memory: scalar
+// loads, no VGPRs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void force_cheb64(const SiteCtx<double>& ctx, double c1, double s1,
+                                             int y, double& Fx, double& Fy) {
+    using T = double;
+    const int K = ctx.K;
+    Fx = 0;
+    Fy = 0;
+    if (K < 0) return;                  // this lattice is unforced
+    const kp<const T> grow = (kp<const T>)ctx.gtab + (size_t)y * (K + 1) * 4;
+    Fx = grow[0];
+    Fy = grow[2];
+    T cp = 1, sp = 0, ck = c1, sk = s1;
+    const T two_c1 = c1 + c1;
+    auto term = [&](T g0, T g1, T g2, T g3) {
+        Fx = fma(ck, g0, fma(-sk, g1, Fx));
+        Fy = fma(ck, g2, fma(-sk, g3, Fy));
+        const T cn = fma(two_c1, ck, -cp);
+        const T sn = fma(two_c1, sk, -sp);
+        cp = ck; sp = sk; ck = cn; sk = sn;
+    };
+    // Batches of RB table rows: one round of scalar loads per batch.  Every
+    // table buffer has kTableSlack values after its last row, so the last
+    // batch may reach past row K; those values are never used.
+    constexpr int RB = 4;
+    static_assert(4 * (RB - 1) <= kTableSlack, "a batch may reach 4 RB - 4 values past row K");
+    int k = 1;
+    for (; k + RB - 1 <= K; k += RB) {
+        T gv[4 * RB];
+#pragma unroll
+        for (int i = 0; i < 4 * RB; ++i) gv[i] = grow[4 * k + i];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
+    }
+    if (k <= K) {
+        T gv[4 * RB];
+#pragma unroll
+        for (int i = 0; i < 4 * RB; ++i) gv[i] = grow[4 * k + i];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+            if (k + i <= K) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force field, FP32 path: the same sum as a dot product of length J over the
+// terms j = 2k (cos(k a), coefficient P_c(k, y)) and j = 2k + 1 (sin(k a),
+// coefficient -Q_c(k, y)), J = 2 (K + 1) rounded up to 16 with zero terms.
+// The basis cos/sin(k a) is a per-lattice table [nx][J] (FP32, rounded from
+// FP64 values at the exactly reduced angles 2 pi (k x mod nx) / nx); the
+// coefficients are the per-step table [ny][J / 16][16][2] (c = x, y).
+// Four sums at once by v_mfma_f32_4x4x1_16b_f32: with the A operand of block
+// ABID broadcast to all 16 blocks, lane 4 t + m supplies coefficient m of term
+// 16 c + t and every lane its own basis value, and lane l accumulates
+//   acc[m] = fma(C_m[j], B_j(x_l), acc[m])   for j = 0, 1, ..., J - 1
+// (each MFMA of K = 1 is one fused multiply-add per output, single rounding),
+// i.e. the same FP32 chain in every kernel form.  The four outputs are two
+// (Fx, Fy) pairs whose coefficients the lanes load: m = 0, 1 from one table
+// row, m = 2, 3 from another (two rows, or two steps).
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kForceChunk = 16;       // basis terms per A-operand register
+
+// 16 terms of chunk c: a = this lane's coefficient register, b = this lane's
+// 16 basis values
+__device__ __forceinline__ v4f force_chunk(v4f acc, float a, const v4f (&b)[4]) {
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[0][0], acc, 4, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[0][1], acc, 4, 1, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[0][2], acc, 4, 2, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[0][3], acc, 4, 3, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[1][0], acc, 4, 4, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[1][1], acc, 4, 5, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[1][2], acc, 4, 6, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[1][3], acc, 4, 7, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[2][0], acc, 4, 8, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[2][1], acc, 4, 9, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[2][2], acc, 4, 10, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[2][3], acc, 4, 11, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[3][0], acc, 4, 12, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[3][1], acc, 4, 13, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[3][2], acc, 4, 14, 0);
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[3][3], acc, 4, 15, 0);
+    return acc;
+}
+
+// Per-lane addressing of the coefficient loads: lane 4 t + m reads component
+// m % 2 of term 16 c + t from row A (m < 2) or row B (m >= 2).
+struct ForceLane {
+    uint32_t off;         // 2 t + m % 2 (floats)
+    bool hi;              // m >= 2
+    __device__ void init(int lane) {
+        off = (uint32_t)(2 * (lane >> 2) + (lane & 1));
+        hi = (lane & 2) != 0;
+    }
+};
+
+// The whole sum with the coefficient registers loaded here (one global load
+// per chunk), for forms whose lanes read their basis from the global table:
+// rowA / rowB point at the coefficient rows of the two output pairs, bas at
+// this lane's basis row [J].
+__device__ __forceinline__ v4f force_sum_global(const float* rowA, const float* rowB,
+                                                const float* bas, int nch, const ForceLane& fl) {
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    const gp<const float> row = (gp<const float>)(fl.hi ? rowB : rowA);
+    const gp<const v4f> b4 = (gp<const v4f>)bas;
+    for (int c = 0; c < nch; ++c) {
+        const float a = row[32 * c + fl.off];
+        v4f b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = b4[4 * c + i];
+        acc = force_chunk(acc, a, b);
+    }
+    return acc;
+}
+
 // sink(qc, r) receives population qc (a std::integral_constant) of the new
 // state as the storage value r = raw(F_q - shift): the collision's last
-// multiply-add, rounded to the storage type by S::fma_round.
+// multiply-add, rounded to the storage type by S::fma_round.  (Fx, Fy) is the
+// stirring force at the site (zero when unforced).
 template <class S, class St, bool FORCED, class T, class Sink>
-__device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
-                                               T s1, int y, Sink&& sink, int* d_flag) {
+__device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCtx<T>& ctx, T Fx,
+                                               T Fy, Sink&& sink, int* d_flag) {
     constexpr int D = St::D;
     const T ginv = ctx.ginv, dt = ctx.dt;
-    const int K = ctx.K;
-    const T* gtab = ctx.gtab;
     // (c) moments, Landau frame in FP64
     const Moments<T> m = moments<St, FORCED>(f);
     const double E64 = (double)m.E + (double)S::shift;
@@ -449,47 +570,6 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
     // force term: dF(v) = a + b.v + v.M.v (Sec. III C, App. B)
     T fa = 0, fbx = 0, fby = 0, Mxx = 0, Mxy = 0, Myy = 0, Mzz = 0;
     if constexpr (FORCED) {
-        // F_c(x, y) = sum_k cos(k a) P_c(k, y) - sin(k a) Q_c(k, y), a = 2 pi x / nx;
-        // cos/sin(k a) by the Chebyshev recurrence.
-        T Fx = 0, Fy = 0;
-        if (K >= 0) {                       // K < 0: this lattice is unforced
-            // The table row of a wave's lattice row is the same for all its lanes and
-            // was written by an earlier launch (a launch only writes the tables of
-            // later steps), so it is read as constant memory: scalar loads, no VGPRs.
-            const kp<const T> grow = (kp<const T>)gtab + (size_t)y * (K + 1) * 4;
-            Fx = grow[0];
-            Fy = grow[2];
-            T cp = 1, sp = 0, ck = c1, sk = s1;
-            const T two_c1 = c1 + c1;
-            auto term = [&](T g0, T g1, T g2, T g3) {
-                Fx = fma(ck, g0, fma(-sk, g1, Fx));
-                Fy = fma(ck, g2, fma(-sk, g3, Fy));
-                const T cn = fma(two_c1, ck, -cp);
-                const T sn = fma(two_c1, sk, -sp);
-                cp = ck; sp = sk; ck = cn; sk = sn;
-            };
-            // Batches of RB table rows (32 values): one round of scalar loads per
-            // batch.  Every table buffer has kTableSlack values after its last row,
-            // so the last batch may reach past row K; those values are never used.
-            constexpr int RB = sizeof(T) == 8 ? 4 : 8;
-            static_assert(4 * (RB - 1) <= kTableSlack, "a batch may reach 4 RB - 4 values past row K");
-            int k = 1;
-            for (; k + RB - 1 <= K; k += RB) {
-                T gv[4 * RB];
-#pragma unroll
-                for (int i = 0; i < 4 * RB; ++i) gv[i] = grow[4 * k + i];
-#pragma unroll
-                for (int i = 0; i < RB; ++i) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
-            }
-            if (k <= K) {
-                T gv[4 * RB];
-#pragma unroll
-                for (int i = 0; i < 4 * RB; ++i) gv[i] = grow[4 * k + i];
-#pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    if (k + i <= K) term(gv[4 * i], gv[4 * i + 1], gv[4 * i + 2], gv[4 * i + 3]);
-            }
-        }
         const T E = (T)E64;
         fa = (T)(-0.5) * dt * fma(Fx, m.Jx, Fy * m.Jy);
         fbx = dt * E * Fx;
@@ -580,13 +660,12 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
 // STREAM: non-temporal stores, for lattices far larger than the caches (the
 // new state is not read again before the whole lattice has been swept).
 template <class S, class St, bool FORCED, bool STREAM = false, class T>
-__device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T>& ctx, T c1,
-                                            T s1, int y, gp<char> drow, uint32_t own,
-                                            int* d_flag) {
+__device__ __forceinline__ void update_site(const T (&f)[St::Q], const SiteCtx<T>& ctx, T Fx,
+                                            T Fy, gp<char> drow, uint32_t own, int* d_flag) {
     using raw = typename S::raw;
     constexpr long long plane_bytes = kTileW * sizeof(raw);
     update_site_to<S, St, FORCED>(
-        f, ctx, c1, s1, y,
+        f, ctx, Fx, Fy,
         [&](auto qc, raw r) {
             constexpr int q = decltype(qc)::value;
             const gp<raw> p = (gp<raw>)(drow + (long long)q * plane_bytes + own);
@@ -707,11 +786,22 @@ __device__ void force_item(const RealDesc& Dsc, int local_item, int64_t step, in
     }
     if (y < ny) {
         const gp<T> g = (gp<T>)uni((T*)Dsc.g[(int)(step & 3)]);
-        const size_t o = ((size_t)y * K1 + k) * 4;
-        g[o + 0] = Px;
-        g[o + 1] = Qx;
-        g[o + 2] = Py;
-        g[o + 3] = Qy;
+        if constexpr (std::is_same<T, double>::value) {
+            // [ny][K+1][4] = (Px, Qx, Py, Qy)
+            const size_t o = ((size_t)y * K1 + k) * 4;
+            g[o + 0] = Px;
+            g[o + 1] = Qx;
+            g[o + 2] = Py;
+            g[o + 3] = Qy;
+        } else {
+            // [ny][J][2]: term 2k = (Px, Py), term 2k + 1 = (-Qx, -Qy); the terms
+            // from 2 (K + 1) to J - 1 stay zero
+            const size_t o = (size_t)y * 2 * uni(Dsc.J) + 4 * (size_t)k;
+            g[o + 0] = Px;
+            g[o + 1] = Py;
+            g[o + 2] = -Qx;
+            g[o + 3] = -Qy;
+        }
     }
 }
 
