@@ -270,6 +270,8 @@ def workload_forms(rl, torch, wl, keys, steps, warmup, chunk, prof_n, tune_steps
         lat.close()
         del lat
         torch.cuda.empty_cache()
+        tag = f"{wl.name}_{storage}" + ("_SPH26_ZFOLD" if fold else "")
+        r["traffic_bytes_per_launch"] = committed_traffic(tag, r["kernel_form"][0])
         out[key] = r
         log(f"{wl.name} {key}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms'] * 1e3:.2f} us "
             f"({r['kernel_form'][0]}:{r['kernel_form'][1]}) = {r['kernel_gbs']:.0f} GB/s "
@@ -503,6 +505,7 @@ def main():
 
     kname = KERNEL_NAMES[head["kernel_form"][0]]
     traffic = committed_traffic("forced8192_F32", head["kernel_form"][0])
+    head["traffic_bytes_per_launch"] = traffic
     roofline = {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["kernel_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,

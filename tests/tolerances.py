@@ -22,8 +22,9 @@ F32_ULPS = 16
 
 # The force increment alone (the rest-state probe: at eps = 1, beta = 0 every
 # other part of the step is exact): its FP32 synthesis error relative to the
-# largest increment of the sample.
-REST_F32_REL = 2e-5
+# largest increment of the sample.  Measured on the GPU: 1.8e-7 (2048^2) and
+# 2.7e-7 (8192^2, 41 table rows).
+REST_F32_REL = 4e-6
 
 
 def ulp32(scale):
