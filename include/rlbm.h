@@ -289,9 +289,11 @@ int rlbm_stream_copy(const void* d_src, void* d_dst, size_t bytes, int32_t reps,
  *                         halo columns) into LDS with aligned row loads, then
  *                         every site streams from LDS; param = 4 (or 0).
  *   RLBM_KERNEL_MARCH_PAIRS -- F16S and BF16S storage only: as RLBM_KERNEL_MARCH
- *                         with every lane on two adjacent columns of a
- *                         128-column strip, so that each load and store moves
- *                         a 32-bit pair; param as for RLBM_KERNEL_MARCH.
+ *                         with every lane on two adjacent columns, so that
+ *                         each load and store moves a 32-bit pair of a
+ *                         128-column strip; param as for RLBM_KERNEL_MARCH.
+ *                         Needs an even nx on every lattice (EUNSUPPORTED
+ *                         otherwise; the autotuner then skips it).
  *   RLBM_KERNEL_MARCH2 -- two time steps per launch: each wavefront marches
  *                         down a 62-column strip computing the first step
  *                         into registers and the second from them, so every

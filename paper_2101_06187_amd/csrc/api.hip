@@ -221,6 +221,12 @@ struct Engine {
     // The marching forms hold at most kMaxMarchJ force terms per row in
     // registers and LDS (forcing shells with |kx| <= 63).
     static constexpr int kMaxMarchJ = 128;
+    // the paired marching form keeps two adjacent columns per lane
+    bool even_nx() const {
+        for (const rlbm_lattice& l : lats)
+            if (l.nx & 1) return false;
+        return true;
+    }
     bool kind_fits(int kind) const {
         return kind == kKernelTile || kind == kKernelStaged || storage == RLBM_F64 ||
                maxJ <= kMaxMarchJ;
@@ -1210,6 +1216,8 @@ int engine_set_kernel(Engine& E, int32_t kind, int32_t param) {
             return fail(RLBM_EUNSUPPORTED, "the row-marching forms need forcing modes with |kx| <= 63");
         if (E.storage != RLBM_F16S && E.storage != RLBM_BF16S)
             return fail(RLBM_EUNSUPPORTED, "the paired marching form is for 16-bit storage");
+        if (!E.even_nx())
+            return fail(RLBM_EUNSUPPORTED, "the paired marching form needs an even nx");
         E.cfg[0].kind = kKernelMarchPair;
         E.cfg[0].seglen_req = param;
         E.pairs = false;
@@ -1306,7 +1314,7 @@ int engine_autotune(Engine& E, int32_t steps, int32_t* h_th) {
     int rc = RLBM_OK;
     for (const auto& c : cand) {
         if (c[0] != RLBM_KERNEL_TILE && E.smode == kStreamHalo2) continue;
-        if (c[0] == RLBM_KERNEL_MARCH_PAIRS && !bits16) continue;
+        if (c[0] == RLBM_KERNEL_MARCH_PAIRS && (!bits16 || !E.even_nx())) continue;
         if (c[0] != RLBM_KERNEL_TILE && c[0] != RLBM_KERNEL_STAGED && !E.kind_fits(kKernelMarch))
             continue;
         if (c[0] == RLBM_KERNEL_MARCH2 && min_ny < 3) continue;

@@ -89,21 +89,28 @@ __device__ __forceinline__ void load_coefs(float (&cf)[kCoefRegs], const float* 
         if (c < nch) cf[c] = row[kForceChunk * 2 * c];
 }
 
-// The four sums of this lane's strip column col (basis in LDS, W columns).
+// The four sums over jt terms of this lane's strip column col (basis in LDS,
+// W columns); nch = ceil(jt / 16) chunks.
 __device__ __forceinline__ v4f force_sum_lds(const float (&cf)[kCoefRegs], const float* rowA,
-                                             const float* rowB, int nch, int col, int W,
+                                             const float* rowB, int jt, int col, int W,
                                              const ForceLane& fl) {
     v4f acc = {0.f, 0.f, 0.f, 0.f};
+    const int nch = (jt + kForceChunk - 1) / kForceChunk;
+    const int tail = force_tail(jt);
     auto basis = [&](int c, v4f (&b)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) b[i] = lds_basis[(4 * c + i) * W + col];
     };
 #pragma unroll
     for (int c = 0; c < kCoefRegs; ++c) {
-        if (c < nch) {
+        if (c + 1 < nch) {
             v4f b[4];
             basis(c, b);
             acc = force_chunk(acc, cf[c], b);
+        } else if (c + 1 == nch) {
+            v4f b[4];
+            basis(c, b);
+            acc = force_chunk_n(acc, cf[c], b, tail);
         }
     }
     if (nch > kCoefRegs) {
@@ -111,7 +118,7 @@ __device__ __forceinline__ v4f force_sum_lds(const float (&cf)[kCoefRegs], const
         for (int c = kCoefRegs; c < nch; ++c) {
             v4f b[4];
             basis(c, b);
-            acc = force_chunk(acc, row[kForceChunk * 2 * c], b);
+            acc = force_chunk_n(acc, row[kForceChunk * 2 * c], b, c + 1 < nch ? kForceChunk : tail);
         }
     }
     return acc;
@@ -125,12 +132,14 @@ __device__ __forceinline__ v4f force_sum_lds(const float (&cf)[kCoefRegs], const
 // column cols[i].  For the one-step marching forms, whose wavefronts issue far
 // more vector-ALU work per force sum than the two-step form.
 template <int NC>
-__device__ __forceinline__ void force_sum_valu(const float* row, int J, const int (&cols)[NC],
+__device__ __forceinline__ void force_sum_valu(const float* row, int jt, const int (&cols)[NC],
                                                int W, float (&F)[2 * NC]) {
     const kp<const float> r = (kp<const float>)row;
 #pragma unroll
     for (int i = 0; i < 2 * NC; ++i) F[i] = 0.f;
-    for (int c = 0; c < J / kForceChunk; ++c) {
+    const int nch = (jt + kForceChunk - 1) / kForceChunk;
+    // chunk c, its first n terms
+    auto chunk = [&](int c, auto all, int n) {
         float cv[2 * kForceChunk];
 #pragma unroll
         for (int i = 0; i < 2 * kForceChunk; ++i) cv[i] = r[2 * kForceChunk * c + i];
@@ -142,14 +151,18 @@ __device__ __forceinline__ void force_sum_valu(const float* row, int J, const in
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int t = 4 * g + i;
+                if (decltype(all)::value || t < n) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    F[2 * k] = fmaf(cv[2 * t], b[k][i], F[2 * k]);
-                    F[2 * k + 1] = fmaf(cv[2 * t + 1], b[k][i], F[2 * k + 1]);
+                    for (int k = 0; k < NC; ++k) {
+                        F[2 * k] = fmaf(cv[2 * t], b[k][i], F[2 * k]);
+                        F[2 * k + 1] = fmaf(cv[2 * t + 1], b[k][i], F[2 * k + 1]);
+                    }
                 }
             }
         }
-    }
+    };
+    for (int c = 0; c + 1 < nch; ++c) chunk(c, std::true_type{}, kForceChunk);
+    chunk(nch - 1, std::false_type{}, force_tail(jt));
 }
 
 // Work items of the marching forms: a block's four wavefronts take four
@@ -278,7 +291,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
             if (K >= 0) {
                 const float* row = (const float*)gtab + (size_t)y * 2 * J;
                 const v4f acc = force_sum_global(row, row, bas + (size_t)min(x, nx - 1) * J,
-                                                 J / kForceChunk, fl);
+                                                 2 * (K + 1), fl);
                 Fx = acc[0];
                 Fy = acc[1];
             }
@@ -527,7 +540,7 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
             if (K >= 0 && y < ny) {
                 const float* row = (const float*)gtab + (size_t)y * 2 * J;
                 const v4f acc = force_sum_global(row, row, bas + (size_t)min(x0 + lx, nx - 1) * J,
-                                                 J / kForceChunk, fl);
+                                                 2 * (K + 1), fl);
                 Fx = acc[0];
                 Fy = acc[1];
             }
@@ -841,7 +854,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
             if constexpr (MF) {
                 if (K >= 0) {
                     float F[2];
-                    force_sum_valu(gsf + (size_t)y * 2 * J, J, cols, kTileW, F);
+                    force_sum_valu(gsf + (size_t)y * 2 * J, 2 * (K + 1), cols, kTileW, F);
                     Fx = F[0];
                     Fy = F[1];
                 }
@@ -878,28 +891,39 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Paired row-marching form, for the 16-bit storage forms.  As march_kernel,
-// but every lane owns two adjacent columns (2 l, 2 l + 1) of a 128-column
-// strip: each load and store moves one 32-bit pair, so a wavefront's memory
-// instruction carries 256 bytes -- as many as in the FP32 form -- instead of
-// 128.  The window holds the pairs packed.  Horizontal neighbours: for a
-// population with c_x > 0 column 2 l takes the high half of lane l - 1's pair
-// and column 2 l + 1 the lane's own low half; with c_x < 0 column 2 l + 1
-// takes the low half of lane l + 1's pair and column 2 l the own high half --
-// one lane exchange per population; the strip's edge columns take the halo
-// columns as in march_kernel.
-// Both sites of a lane go through the same update_site as every other form,
-// so the results are bitwise identical.
-// The lane computes column A, then column B, so one site's streamed
-// populations are live at a time, and asks for three wavefronts per SIMD
-// (at most 168 VGPRs; the forced 26-velocity kernel spills a few values):
-// a 16-bit lattice larger than the caches is bound by the bytes in flight,
-// and this form keeps 26 x 256 bytes in flight per wavefront (measured at
-// 8192^2 F16S: 1.91 ms per step, 2.08 ms with two wavefronts per SIMD,
-// 2.09 ms for the one-column form).
+// Paired row-marching form, for the 16-bit storage forms.  Every lane owns
+// two adjacent columns of a 128-column strip, so each load and store moves an
+// aligned 32-bit pair (256 bytes per wavefront instruction, two whole cache
+// lines, as in the FP32 forms).  Needs even nx: the strip's last column is
+// then always the high half of a pair.  With column A = 2 l (the low half)
+// and column B = 2 l + 1 (the high half) of lane l:
+//   c_x > 0: A pulls from the high half of lane l - 1, B from its low half;
+//   c_x < 0: A pulls from its high half, B from the low half of lane l + 1;
+// the lane exchanges are DPP wave shifts.  Lanes past the lattice's last
+// column hold the periodically wrapped columns, so in a ragged last strip the
+// last column's right neighbour (column 0) comes from the next lane; the
+// strip's halo columns x0 - 1 and x0 + 128 enter as the DPP shift's value for
+// the lane without a source lane (0 or 63): one gathered load per row (lane j
+// holds the halo of the j-th population with c_x != 0), read out by
+// v_readlane.
+// The lane streams and updates column A, then column B, so one site's
+// streamed populations are live at a time; column B's new populations go
+// into the high halves of the words that hold column A's (S::pk_first /
+// pk_second).  Both sites go through the same per-site update as every other
+// form, so the results are bitwise identical.
+// Stirring force: the sums of force_chunk (site.hpp) on the matrix cores,
+// two chains (columns A and B) over the same coefficient registers and two
+// rows at a time (outputs 0, 1: row y; 2, 3: row y + 1), in every other row
+// iteration after its loads are issued, from coefficients loaded at the start
+// of the iteration before, ahead of its population loads: a whole row
+// iteration hides their latency, and waiting for them never waits for a
+// population row.  The strip's basis sits in LDS as [J/4][A, B][lane] (16-byte reads
+// without bank conflicts).
+// Two wavefronts per SIMD: with three (at most 168 VGPRs) the forced kernel
+// spills, and 8192^2 F16S ran 14 % slower.
 // ---------------------------------------------------------------------------
 template <class S, class St, int SM, bool FORCED>
-__global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
+__global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
     static_assert(SM != kStreamHalo2, "the row-marching form streams from the nearest rows only");
     static_assert(sizeof(typename S::raw) == 2, "pairs of 16-bit populations");
     constexpr bool UNIT = SM == kStreamUnit;
@@ -907,13 +931,15 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
     using raw = typename S::raw;
     using M = MarchMap<St>;
     constexpr int Q = St::Q;
-    constexpr int NH = M::nH();
     constexpr int kW = 2 * kTileW;              // columns per strip
+    constexpr int NH = M::nH();
 
     const int64_t step = A.d_step[0] + A.step_off;
     const int par = (int)((A.d_step[1] + A.launch_off) & 1);
     const int lane = threadIdx.x;
     const int wv = uni((int)threadIdx.y);
+    ForceLane fl;
+    fl.init(lane);
 
     const int G = A.tile_blocks;
     const int b = blockIdx.x;
@@ -923,10 +949,16 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
     const int chunk = (n_groups + 7) >> 3;
     const int g_end = min(n_groups, (xcd + 1) * chunk);
 
-    auto half_lo = [](uint32_t u) -> T { return S::from_bits((uint16_t)(u & 0xffffu)); };
-    auto half_hi = [](uint32_t u) -> T { return S::from_bits((uint16_t)(u >> 16)); };
-    auto pair_from = [](uint32_t u, int addr_bytes) -> uint32_t {
-        return (uint32_t)__builtin_amdgcn_ds_bpermute(addr_bytes, (int)u);
+    // x-neighbours: the pair of lane l - 1 (wave_shr:1) or l + 1 (wave_shl:1);
+    // the lane without a source lane (0 or 63) takes edge
+    auto from_left = [](uint32_t v, uint32_t edge) -> uint32_t {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xf, 0xf, false);
+    };
+    auto from_right = [](uint32_t v, uint32_t edge) -> uint32_t {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xf, 0xf, false);
+    };
+    auto halo_bits = [](uint32_t h, int l) -> uint32_t {
+        return (uint32_t)__builtin_amdgcn_readlane((int)h, l);
     };
 
     // The loop over groups is uniform over the block (the basis barriers).
@@ -935,32 +967,33 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
         const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
-        const int pitch = uni(Dsc.pitch);
         MarchItem it;
         it.decode(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
                   uni(Dsc.wm[A.map].seglen));
         const int ya = it.ya, yb = it.yb;
         const int x0 = it.strip * kW;
+        const int Rc = min(kW - 1, nx - 1 - x0);        // last column of the strip (odd)
+        const int Lr = Rc >> 1;                         // its lane
+        const int xa = x0 + 2 * lane;                   // this lane's columns xa, xa + 1
+        const bool out_lane = lane <= Lr;
+        const int xw = xa < nx ? xa : xa % nx;          // wrapped past the lattice
         int K = -1, J = 0;
         if constexpr (FORCED) {
             K = uni(Dsc.K);
             J = uni(Dsc.J);
-            // this strip's force basis (128 columns), shared by the block's
-            // four wavefronts; columns past the lattice take its last column's
+            // this strip's force basis, shared by the block's four wavefronts:
+            // position p < 64 holds column A of lane p, 64 + p column B
+            // (columns past the lattice take its last column's)
             __syncthreads();
             if (K >= 0)
-                stage_basis(uni(Dsc.bas), J, kW, [&](int col) { return min(x0 + col, nx - 1); });
+                stage_basis(uni(Dsc.bas), J, kW, [&](int pos) {
+                    return min(x0 + (pos < kTileW ? 2 * pos : 2 * (pos - kTileW) + 1), nx - 1);
+                });
             __syncthreads();
         }
         if (!it.rows) continue;
-        const int Rc = min(kW - 1, nx - 1 - x0);        // last column of the strip
-        const int Lr = Rc >> 1;                         // lane of the last column
-        const bool last_is_b = (Rc & 1) != 0;
-        const int xa = x0 + 2 * lane;                   // this lane's columns xa, xa + 1
-        const bool activeA = 2 * lane <= Rc;
-        const bool activeB = 2 * lane + 1 <= Rc;
         constexpr long long plane_bytes = kTileW * sizeof(raw);
-        const long long rowq = (long long)pitch * Q * (long long)sizeof(raw);
+        const long long rowq = (long long)uni(Dsc.pitch) * Q * (long long)sizeof(raw);
         const char* src = (const char*)uni(Dsc.buf[par]);
         char* dst = (char*)uni(Dsc.buf[par ^ 1]);
         InterpW<T> W;
@@ -972,58 +1005,84 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
         sctx.eta_s = uni(Dsc.tau_mode);
         sctx.gtab = nullptr;
         if constexpr (FORCED) sctx.gtab = uni((const T*)Dsc.g[step & 3]);
-        // force sums of columns A and B on the vector ALU (basis in LDS)
-        const float* gsf = (const float*)sctx.gtab;
-        const int cols[2] = {2 * lane, 2 * lane + 1};
-        // the pair's byte offset in a row; lanes past the padded row read its last pair
-        const uint32_t colb = col_bytes<raw>(min(xa, pitch - 2), Q);
+        const uint32_t colb = col_bytes<raw>(xw, Q);
         auto wrap = [&](int yy) { return yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy); };
+        // uniform row base (scalar registers), the lane's column as a 32-bit offset
         auto ld = [&](int q, int yy) -> uint32_t {
             const char* rowp = src + (long long)wrap(yy) * rowq + (long long)q * plane_bytes;
             return *(gp<const uint32_t>)(rowp + colb);
         };
-        int my_q = 0, my_dy = 0;
+        // halo gather of row yy: lane j < NH holds the 16 bits of the halo of
+        // the j-th population with c_x != 0 at row yy -- column x0 - 1
+        // (c_x > 0) or x0 + 128 (c_x < 0), wrapped (the other lanes read a
+        // value they do not use)
+        int my_q = 0;
         bool my_left = true;
         sfor<0, Q>([&](auto iq) {
             constexpr int q = decltype(iq)::value;
             if constexpr (M::cx(q) != 0) {
                 if (lane == M::hidx(q)) {
                     my_q = q;
-                    my_dy = M::cy(q) < 0 ? 1 : 0;
                     my_left = M::cx(q) > 0;
                 }
             }
         });
-        const int hcol = my_left ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + Rc + 1 == nx ? 0 : x0 + Rc + 1);
-        auto gather = [&](int yy) -> uint32_t {       // the halo's 16 bits
-            uint32_t h = 0;
-            if (lane < NH) {
-                const char* p = src + (long long)wrap(yy + my_dy) * rowq +
-                                (long long)my_q * plane_bytes + col_bytes<raw>(hcol, Q);
-                h = *(gp<const uint16_t>)p;
-            }
-            return h;
-        };
-        auto halo_bits = [](uint32_t h, int l) -> uint32_t {
-            return (uint32_t)__builtin_amdgcn_readlane((int)h, l);
-        };
-        // The strip's edge columns take their x-neighbour from the halo.  The
-        // halo enters the lane exchange through the lane that the edge lane
-        // reads -- lane 63's high half for the left halo (lane 0 reads lane 63),
-        // lane Lr + 1's low half for the right halo -- so the permute's result
-        // is used on every lane as it is: a select after the permute lets the
-        // compiler run it under a mask without the edge lane, whose data the
-        // neighbouring lane then does not receive.
-        const int rl = (Lr + 1) & 63;
-        auto left_of = [&](uint32_t v, uint32_t hb) -> T {        // column 2 l - 1
-            const uint32_t s = lane == 63 ? ((v & 0xffffu) | (hb << 16)) : v;
-            return half_hi(pair_from(s, ((lane - 1) & 63) * 4));
-        };
-        auto right_of = [&](uint32_t v, uint32_t hb) -> T {       // column 2 l + 2
-            const uint32_t s = (last_is_b && lane == rl) ? ((v & 0xffff0000u) | hb) : v;
-            return half_lo(pair_from(s, ((lane + 1) & 63) * 4));
+        const int hcol = my_left ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + kW) % nx;
+        const uint32_t hoff = (uint32_t)my_q * (uint32_t)plane_bytes + col_bytes<raw>(hcol, Q);
+        auto gather = [&](int yy) -> uint32_t {
+            const char* rowp = src + (long long)wrap(yy) * rowq;
+            return *(gp<const uint16_t>)(rowp + hoff);
         };
 
+        // force coefficients of rows yy, yy + 1 (the segment's last row for
+        // rows past it): lane 4 t + m holds component m % 2 of term 16 c + t of
+        // row yy (m < 2) or yy + 1 (m >= 2) in cf[c]; the first kPairCoefs
+        // chunks (|kx| <= 47) are loaded ahead, further chunks where they are
+        // used.  Rows yy and yy + 1 are adjacent in the table.
+        constexpr int kPairCoefs = 6;
+        const int jt = 2 * (K + 1);                     // terms that are not zero
+        const int nch = J / kForceChunk;
+        const float* gsf = (const float*)sctx.gtab;
+        auto coef_row = [&](int yy) { return (gp<const float>)(gsf + (size_t)yy * 2 * J); };
+        auto coef_off = [&](int yy) {      // this lane's offset from row yy (floats)
+            return fl.off + (fl.hi && yy + 1 < yb ? 2u * (uint32_t)J : 0u);
+        };
+        float cf[kPairCoefs];
+        auto load_row_coefs = [&](int yy) {
+            const gp<const float> row = coef_row(yy);
+            const uint32_t o = coef_off(yy);
+#pragma unroll
+            for (int c = 0; c < kPairCoefs; ++c)
+                cf[c] = row[kForceChunk * 2 * min(c, nch - 1) + o];
+        };
+        v4f FA = {0.f, 0.f, 0.f, 0.f}, FB = {0.f, 0.f, 0.f, 0.f};
+        // FA / FB = (Fx, Fy) of columns A / B at rows yy (0, 1) and yy + 1 (2, 3)
+        auto force_rows = [&](int yy) {
+            FA = {0.f, 0.f, 0.f, 0.f};
+            FB = {0.f, 0.f, 0.f, 0.f};
+            auto chunk = [&](int c, float a, auto all, int n) {
+                v4f bA[4], bB[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    bA[i] = lds_basis[(4 * c + i) * kW + lane];
+                    bB[i] = lds_basis[(4 * c + i) * kW + kTileW + lane];
+                }
+                force_chunk2<decltype(all)::value>(FA, FB, a, bA, bB, n);
+            };
+            const int tail = force_tail(jt);
+#pragma unroll
+            for (int c = 0; c < kPairCoefs; ++c) {
+                if (c + 1 < nch) chunk(c, cf[c], std::true_type{}, kForceChunk);
+                else if (c + 1 == nch) chunk(c, cf[c], std::false_type{}, tail);
+            }
+            for (int c = kPairCoefs; c < nch; ++c)
+                chunk(c, coef_row(yy)[kForceChunk * 2 * c + coef_off(yy)], std::false_type{},
+                      c + 1 < nch ? kForceChunk : tail);
+        };
+
+        if constexpr (FORCED) {
+            if (K >= 0) load_row_coefs(ya);
+        }
         uint32_t cur[Q], pre[Q], up[M::nU], dn[M::nD];
         sfor<0, Q>([&](auto iq) {
             constexpr int q = decltype(iq)::value;
@@ -1031,27 +1090,36 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
             if constexpr (M::cy(q) > 0) up[M::uidx(q)] = ld(q, ya - 1);
             if constexpr (M::cy(q) < 0) dn[M::didx(q)] = ld(q, ya + 1);
         });
-        uint32_t hp = gather(ya - 1);
-        uint32_t hc = gather(ya);
-        uint32_t hn = 0;
+        // halo rows y - 1, y, y + 1 and (in flight) y + 2
+        uint32_t hm = gather(ya - 1);
+        uint32_t h0 = gather(ya);
+        uint32_t h1 = gather(ya + 1);
+        uint32_t h2 = 0;
 
         for (int y = ya; y < yb; ++y) {
-            if (y + 1 < yb) {
-                sfor<0, Q>([&](auto iq) {
-                    constexpr int q = decltype(iq)::value;
-                    pre[q] = ld(q, M::cy(q) < 0 ? y + 2 : y + 1);
-                });
-                hn = gather(y + 1);
-            }
-            // (b)-(e) column A, then column B: one site's streamed populations
-            // are live at a time.  The lane exchanges run on every lane (the
-            // permutes sit outside the activity branches).
-            float FAB[4] = {0.f, 0.f, 0.f, 0.f};  // (Fx, Fy) of column A, of column B
+            const bool even = ((y - ya) & 1) == 0;
+            // the coefficients of rows y + 1, y + 2, ahead of this row's loads
             if constexpr (FORCED) {
-                if (K >= 0) force_sum_valu(gsf + (size_t)y * 2 * J, J, cols, kW, FAB);
+                if (K >= 0 && !even) load_row_coefs(min(y + 1, yb - 1));
             }
+            // the next row in flight; issued in every iteration (past the
+            // segment's rows it repeats its last, which is a cache hit), so
+            // that the compiler's waits can leave these loads in flight
+            sfor<0, Q>([&](auto iq) {
+                constexpr int q = decltype(iq)::value;
+                pre[q] = ld(q, M::cy(q) < 0 ? min(y + 2, yb) : min(y + 1, yb - 1));
+            });
+            h2 = gather(min(y + 2, yb));
+            // the forces of rows y, y + 1 (coefficients loaded an iteration ago)
+            if constexpr (FORCED) {
+                if (K >= 0 && even) force_rows(y);
+            }
+            // column A.  Every lane streams and updates (the lane exchanges
+            // need every lane's window); only the lanes on the lattice raise
+            // the stability flag and store.
             T f[Q];
-            uint32_t outp[Q];                     // the new pairs: A low, B high
+            typename S::pair_tmp tmp[Q];
+            uint32_t outp[Q];
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
                 constexpr Dir d = St::dir[q];
@@ -1060,36 +1128,35 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
                 uint32_t vert = own;
                 if constexpr (d.cy > 0) vert = up[M::uidx(q)];
                 if constexpr (d.cy < 0) vert = dn[M::didx(q)];
-                const T oa = half_lo(own), va = half_lo(vert);
+                const T oa = S::lo(own), va = S::lo(vert);
                 if constexpr (d.cx == 0 && d.cy == 0) {
                     f[q] = oa;
                 } else if constexpr (d.cx == 0) {
                     if constexpr (UNIT && n == 1) f[q] = va;
                     else f[q] = lerp(oa, va, W.a[n - 1]);
                 } else {
-                    // x-neighbour upstream of column A: 2 l - 1 (c_x > 0) or 2 l + 1
+                    // left neighbour of column A: lane l - 1's high half, for
+                    // lane 0 the halo
                     constexpr int H = M::hidx(q);
-                    const uint32_t h_own = halo_bits(d.cy < 0 ? hp : hc, H);   // halo, row y
-                    const T na = d.cx > 0 ? left_of(own, h_own)
-                                          : ((!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_own)
-                                                                        : half_hi(own));
+                    T na;
+                    if constexpr (d.cx > 0) na = S::hi(from_left(own, halo_bits(h0, H) << 16));
+                    else na = S::hi(own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = na;
                         else f[q] = lerp(oa, na, W.a[n - 1]);
                     } else {
-                        const uint32_t h_vert = halo_bits(d.cy > 0 ? hp : hc, H);
-                        const T vna = d.cx > 0 ? left_of(vert, h_vert)
-                                               : ((!last_is_b && lane == Lr) ? S::from_bits((uint16_t)h_vert)
-                                                                             : half_hi(vert));
+                        // the upstream row's: y - 1 or y + 1
+                        T vna;
+                        if constexpr (d.cx > 0) vna = S::hi(from_left(vert, halo_bits(d.cy > 0 ? hm : h1, H) << 16));
+                        else vna = S::hi(vert);
                         f[q] = fma(W.w11[n - 1], vna, fma(W.w10[n - 1], na + va, W.w00[n - 1] * oa));
                     }
                 }
             });
-            if (activeA)
-                update_site_to<S, St, FORCED>(
-                    f, sctx, FAB[0], FAB[1],
-                    [&](auto qc, raw r) { outp[decltype(qc)::value] = __builtin_bit_cast(uint16_t, r); },
-                    A.d_flag);
+            update_site_fma<S, St, FORCED>(
+                f, sctx, FA[0], FA[1],
+                [&](auto qc, T a, T bb, T c) { tmp[decltype(qc)::value] = S::pk_first(a, bb, c); },
+                A.d_flag, out_lane);
             // column B converts the window's halves anew: values kept from column
             // A's pass would stay live through A's update and cost registers
 #pragma unroll
@@ -1106,45 +1173,48 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
                 uint32_t vert = own;
                 if constexpr (d.cy > 0) vert = up[M::uidx(q)];
                 if constexpr (d.cy < 0) vert = dn[M::didx(q)];
-                const T ob = half_hi(own), vb = half_hi(vert);
+                const T ob = S::hi(own), vb = S::hi(vert);
                 if constexpr (d.cx == 0 && d.cy == 0) {
                     f[q] = ob;
                 } else if constexpr (d.cx == 0) {
                     if constexpr (UNIT && n == 1) f[q] = vb;
                     else f[q] = lerp(ob, vb, W.a[n - 1]);
                 } else {
-                    // x-neighbour upstream of column B: 2 l (c_x > 0) or 2 l + 2
+                    // right neighbour of column B: lane l + 1's low half, for
+                    // lane 63 the halo
                     constexpr int H = M::hidx(q);
-                    T nb;
-                    if constexpr (d.cx > 0) nb = half_lo(own);
-                    else nb = right_of(own, halo_bits(d.cy < 0 ? hp : hc, H));
+                    T nbv;
+                    if constexpr (d.cx < 0) nbv = S::lo(from_right(own, halo_bits(h0, H)));
+                    else nbv = S::lo(own);
                     if constexpr (d.cy == 0) {
-                        if constexpr (UNIT && n == 1) f[q] = nb;
-                        else f[q] = lerp(ob, nb, W.a[n - 1]);
+                        if constexpr (UNIT && n == 1) f[q] = nbv;
+                        else f[q] = lerp(ob, nbv, W.a[n - 1]);
                     } else {
                         T vnb;
-                        if constexpr (d.cx > 0) vnb = half_lo(vert);
-                        else vnb = right_of(vert, halo_bits(d.cy > 0 ? hp : hc, H));
-                        f[q] = fma(W.w11[n - 1], vnb, fma(W.w10[n - 1], nb + vb, W.w00[n - 1] * ob));
+                        if constexpr (d.cx < 0) vnb = S::lo(from_right(vert, halo_bits(d.cy > 0 ? hm : h1, H)));
+                        else vnb = S::lo(vert);
+                        f[q] = fma(W.w11[n - 1], vnb, fma(W.w10[n - 1], nbv + vb, W.w00[n - 1] * ob));
                     }
                 }
             });
-            if (activeB)
-                update_site_to<S, St, FORCED>(
-                    f, sctx, FAB[2], FAB[3],
-                    [&](auto qc, raw r) {
-                        constexpr int q = decltype(qc)::value;
-                        outp[q] = (outp[q] & 0xffffu) | ((uint32_t)__builtin_bit_cast(uint16_t, r) << 16);
-                    },
-                    A.d_flag);
-            // one packed store per population; a lane whose column B lies past the
-            // lattice writes +0 into that padding column
-            if (activeA) {
+            update_site_fma<S, St, FORCED>(
+                f, sctx, FB[0], FB[1],
+                [&](auto qc, T a, T bb, T c) {
+                    constexpr int q = decltype(qc)::value;
+                    outp[q] = S::pk_second(tmp[q], a, bb, c);
+                },
+                A.d_flag, out_lane);
+            // row y + 1's forces
+            FA[0] = FA[2];
+            FA[1] = FA[3];
+            FB[0] = FB[2];
+            FB[1] = FB[3];
+            // one 32-bit store per population and pair
+            if (out_lane) {
                 const gp<char> drow = (gp<char>)(dst + (long long)y * rowq);
                 sfor<0, Q>([&](auto iq) {
                     constexpr int q = decltype(iq)::value;
-                    const uint32_t pk = activeB ? outp[q] : (outp[q] & 0xffffu);
-                    __builtin_nontemporal_store(pk, (gp<uint32_t>)(drow + (long long)q * plane_bytes + colb));
+                    __builtin_nontemporal_store(outp[q], (gp<uint32_t>)(drow + (long long)q * plane_bytes + colb));
                 });
             }
             // roll the window
@@ -1160,8 +1230,9 @@ __global__ __launch_bounds__(256, 3) void march_pair_kernel(StepArgs A) {
                     cur[q] = pre[q];
                 }
             });
-            hp = hc;
-            hc = hn;
+            hm = h0;
+            h0 = h1;
+            h1 = h2;
         }
     }
 
@@ -1328,7 +1399,7 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         if constexpr (MF) {
             if (K >= 0) {
                 load_coefs(cf, rowA(r0), rowB(r0), nch, fl);
-                Fsum = force_sum_lds(cf, rowA(r0), rowB(r0), nch, lane, kTileW, fl);
+                Fsum = force_sum_lds(cf, rowA(r0), rowB(r0), 2 * (K + 1), lane, kTileW, fl);
             }
         }
         T cur[Q], up[M::nU], dn[M::nD];           // input rows rr, rr - 1, rr + 1
@@ -1468,7 +1539,7 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             });
             // the forces of the next iteration
             if constexpr (MF) {
-                if (K >= 0) Fsum = force_sum_lds(cf, rowA(rr + 1), rowB(rr + 1), nch, lane, kTileW, fl);
+                if (K >= 0) Fsum = force_sum_lds(cf, rowA(rr + 1), rowB(rr + 1), 2 * (K + 1), lane, kTileW, fl);
             }
         }
     }

@@ -113,6 +113,23 @@ struct StF16S {
     }
     __device__ static double to64(raw v) { return (double)(float)v; }
     __device__ static raw from64(double v) { return (_Float16)(float)v; }
+    // Two adjacent columns in one 32-bit word, the even one in the low half.
+    // pk_first rounds a * b + c into the low half (the high half is left
+    // undefined); pk_second rounds the next column's into the high half of
+    // that word and keeps its low half (v_fma_mixhi_f16: the same single
+    // rounding as fma_round, written to the other half).
+    using pair_tmp = uint32_t;
+    __device__ static pair_tmp pk_first(T a, T b, T c) {
+        uint32_t r;
+        asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+        return r;
+    }
+    __device__ static uint32_t pk_second(pair_tmp w, T a, T b, T c) {
+        asm("v_fma_mixhi_f16 %0, %1, %2, %3" : "+v"(w) : "v"(a), "v"(b), "v"(c));
+        return w;
+    }
+    __device__ static T lo(uint32_t u) { return from_bits((uint16_t)(u & 0xffffu)); }
+    __device__ static T hi(uint32_t u) { return from_bits((uint16_t)(u >> 16)); }
 };
 struct StBF16S {
     using raw = uint16_t;
@@ -129,6 +146,19 @@ struct StBF16S {
     }
     __device__ static double to64(raw v) { return (double)__uint_as_float((uint32_t)v << 16); }
     __device__ static raw from64(double v) { return f32_to_bf16_rne((float)v); }
+    // Two adjacent columns in one 32-bit word, the even one in the low half:
+    // the first column's FP32 multiply-add is kept until the second's, then
+    // both are rounded to nearest even BF16 by one v_cvt_pk_bf16_f32.
+    using pair_tmp = float;
+    __device__ static pair_tmp pk_first(T a, T b, T c) { return fmaf(a, b, c); }
+    __device__ static uint32_t pk_second(pair_tmp w, T a, T b, T c) {
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const f32x2 v = {w, fmaf(a, b, c)};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    }
+    __device__ static T lo(uint32_t u) { return __uint_as_float(u << 16); }
+    __device__ static T hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
 };
 
 // ---------------------------------------------------------------------------
@@ -465,11 +495,12 @@ __device__ __forceinline__ void force_cheb64(const SiteCtx<double>& ctx, double 
 // coefficient -Q_c(k, y)), J = 2 (K + 1) rounded up to 16 with zero terms.
 // The basis cos/sin(k a) is a per-lattice table [nx][J] (FP32, rounded from
 // FP64 values at the exactly reduced angles 2 pi (k x mod nx) / nx); the
-// coefficients are the per-step table [ny][J / 16][16][2] (c = x, y).
+// coefficients are the per-step table [ny][J / 16][16][2] (c = x, y).  The
+// sums run over the jt = 2 (K + 1) terms that are not zero by construction.
 // Four sums at once by v_mfma_f32_4x4x1_16b_f32: with the A operand of block
 // ABID broadcast to all 16 blocks, lane 4 t + m supplies coefficient m of term
 // 16 c + t and every lane its own basis value, and lane l accumulates
-//   acc[m] = fma(C_m[j], B_j(x_l), acc[m])   for j = 0, 1, ..., J - 1
+//   acc[m] = fma(C_m[j], B_j(x_l), acc[m])   for j = 0, 1, ..., jt - 1
 // (each MFMA of K = 1 is one fused multiply-add per output, single rounding),
 // i.e. the same FP32 chain in every kernel form.  The four outputs are two
 // (Fx, Fy) pairs whose coefficients the lanes load: m = 0, 1 from one table
@@ -500,6 +531,35 @@ __device__ __forceinline__ v4f force_chunk(v4f acc, float a, const v4f (&b)[4]) 
     return acc;
 }
 
+// The first n terms of a chunk only (1 <= n <= 16): the chunk holding the
+// forcing's largest wave number ends with zero terms, which are skipped.
+__device__ __forceinline__ v4f force_chunk_n(v4f acc, float a, const v4f (&b)[4], int n) {
+    sfor<0, kForceChunk>([&](auto it) {
+        constexpr int t = decltype(it)::value;
+        if (t < n) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b[t / 4][t % 4], acc, 4, t, 0);
+    });
+    return acc;
+}
+
+// The same for two chains over one coefficient register: accA with the basis
+// values bA, accB with bB (the two columns of a paired lane), interleaved so
+// that each chain's next MFMA does not wait for its previous one; the first n
+// terms of the chunk.
+template <bool ALL>
+__device__ __forceinline__ void force_chunk2(v4f& accA, v4f& accB, float a, const v4f (&bA)[4],
+                                             const v4f (&bB)[4], int n = kForceChunk) {
+    sfor<0, kForceChunk>([&](auto it) {
+        constexpr int t = decltype(it)::value;
+        if (ALL || t < n) {
+            accA = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bA[t / 4][t % 4], accA, 4, t, 0);
+            accB = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bB[t / 4][t % 4], accB, 4, t, 0);
+        }
+    });
+}
+
+// Terms in the last chunk of a sum over jt terms (1 .. 16).
+__device__ __forceinline__ int force_tail(int jt) { return jt - kForceChunk * ((jt - 1) / kForceChunk); }
+
 // Per-lane addressing of the coefficient loads: lane 4 t + m reads component
 // m % 2 of term 16 c + t from row A (m < 2) or row B (m >= 2).
 struct ForceLane {
@@ -511,32 +571,41 @@ struct ForceLane {
     }
 };
 
-// The whole sum with the coefficient registers loaded here (one global load
-// per chunk), for forms whose lanes read their basis from the global table:
-// rowA / rowB point at the coefficient rows of the two output pairs, bas at
-// this lane's basis row [J].
+// The whole sum over the jt = 2 (K + 1) terms with the coefficient registers
+// loaded here (one global load per chunk), for forms whose lanes read their
+// basis from the global table: rowA / rowB point at the coefficient rows of
+// the two output pairs, bas at this lane's basis row [J].
 __device__ __forceinline__ v4f force_sum_global(const float* rowA, const float* rowB,
-                                                const float* bas, int nch, const ForceLane& fl) {
+                                                const float* bas, int jt, const ForceLane& fl) {
     v4f acc = {0.f, 0.f, 0.f, 0.f};
     const gp<const float> row = (gp<const float>)(fl.hi ? rowB : rowA);
     const gp<const v4f> b4 = (gp<const v4f>)bas;
-    for (int c = 0; c < nch; ++c) {
-        const float a = row[32 * c + fl.off];
-        v4f b[4];
+    const int nch = (jt + kForceChunk - 1) / kForceChunk;
+    auto chunk = [&](int c, v4f (&b)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) b[i] = b4[4 * c + i];
+        return row[32 * c + fl.off];
+    };
+    for (int c = 0; c + 1 < nch; ++c) {
+        v4f b[4];
+        const float a = chunk(c, b);
         acc = force_chunk(acc, a, b);
     }
-    return acc;
+    v4f b[4];
+    const float a = chunk(nch - 1, b);
+    return force_chunk_n(acc, a, b, force_tail(jt));
 }
 
-// sink(qc, r) receives population qc (a std::integral_constant) of the new
-// state as the storage value r = raw(F_q - shift): the collision's last
-// multiply-add, rounded to the storage type by S::fma_round.  (Fx, Fy) is the
-// stirring force at the site (zero when unforced).
-template <class S, class St, bool FORCED, class T, class Sink>
-__device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCtx<T>& ctx, T Fx,
-                                               T Fy, Sink&& sink, int* d_flag) {
+// fin(qc, a, b, c) receives population qc (a std::integral_constant) of the
+// new state as the operands of the collision's last multiply-add:
+// F_q - shift = a * b + c, to be rounded once to the storage type (as
+// S::fma_round does).  (Fx, Fy) is the stirring force at the site (zero when
+// unforced).
+// A lane whose result is discarded passes live = false: it does not raise the
+// stability flag.
+template <class S, class St, bool FORCED, class T, class Fin>
+__device__ __forceinline__ void update_site_fma(const T (&f)[St::Q], const SiteCtx<T>& ctx, T Fx,
+                                                T Fy, Fin&& fin, int* d_flag, bool live = true) {
     constexpr int D = St::D;
     const T ginv = ctx.ginv, dt = ctx.dt;
     // (c) moments, Landau frame in FP64
@@ -547,7 +616,7 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
     const bool ok = landau64<D>(E64, (double)m.Jx, (double)m.Jy,
                                 (double)m.Pxx + dshift, (double)m.Pxy,
                                 (double)m.Pyy + dshift, eps, bx64, by64);
-    if (!ok) *d_flag = 1;
+    if (!ok && live) *d_flag = 1;
 
     // (d) equilibrium F_eq - shift = A0' + B t + C t^2 (t = beta.v), and the
     // Anderson-Witting rate omega = g (1 - t), g = gamma / tau.  For the +v
@@ -633,7 +702,7 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
             // v = (0, 0, +-1): t = 0, no odd part, rate omega = g
             sfor<0, Cl.nplus>([&](auto i) {
                 constexpr int q = Cl.first + decltype(i)::value;
-                sink(std::integral_constant<int, q>{}, S::fma_round(omg, f[q], e0));
+                fin(std::integral_constant<int, q>{}, omg, f[q], e0);
             });
         } else {
             const T ep = fma((T)(m * m), SN[di], e0);
@@ -642,18 +711,27 @@ __device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCt
             const T mp = fma(gm[mi], tn[di], omg);
             sfor<0, Cl.nplus>([&](auto i) {
                 constexpr int q = Cl.first + decltype(i)::value;
-                sink(std::integral_constant<int, q>{}, S::fma_round(mp, f[q], Kp));
+                fin(std::integral_constant<int, q>{}, mp, f[q], Kp);
             });
             if constexpr (Cl.nminus > 0) {
                 const T Km = ep - op;
                 const T mm = fma(-gm[mi], tn[di], omg);
                 sfor<0, Cl.nminus>([&](auto i) {
                     constexpr int q = Cl.first + Cl.nplus + decltype(i)::value;
-                    sink(std::integral_constant<int, q>{}, S::fma_round(mm, f[q], Km));
+                    fin(std::integral_constant<int, q>{}, mm, f[q], Km);
                 });
             }
         }
     });
+}
+
+// sink(qc, r) receives population qc of the new state as the storage value
+// r = raw(F_q - shift), the last multiply-add rounded by S::fma_round.
+template <class S, class St, bool FORCED, class T, class Sink>
+__device__ __forceinline__ void update_site_to(const T (&f)[St::Q], const SiteCtx<T>& ctx, T Fx,
+                                               T Fy, Sink&& sink, int* d_flag) {
+    update_site_fma<S, St, FORCED>(
+        f, ctx, Fx, Fy, [&](auto qc, T a, T b, T c) { sink(qc, S::fma_round(a, b, c)); }, d_flag);
 }
 
 // ... storing into global memory: the destination row drow, byte offset own.

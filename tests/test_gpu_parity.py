@@ -604,19 +604,21 @@ def test_ensemble_matches_oracle(kind):
 
 @pytest.mark.parametrize("storage", ["F16S", "BF16S"])
 @pytest.mark.parametrize("shape,cfl,forced", [((96, 104), 1.0, True), ((130, 37), 1.0, True),
-                                              ((37, 9), 0.9, True), ((200, 66), 0.9, False),
+                                              ((38, 9), 0.9, True), ((200, 66), 0.9, False),
                                               ((256, 20), 1.0, True), ((2, 33), 0.9, False),
-                                              ((3, 5), 1.0, False), ((129, 2), 1.0, False)])
+                                              ((4, 5), 1.0, False), ((124, 7), 1.0, True),
+                                              ((126, 2), 1.0, False), ((248, 12), 0.9, True),
+                                              ((250, 6), 1.0, True)])
 def test_paired_form_is_bitwise_equal_to_tile_form(storage, shape, cfl, forced):
-    """The paired marching form (two columns per lane, 128-column strips) on
-    ragged lattices -- the last strip 2, 37, 72 or 128 columns wide, one or
-    both columns of the last lane active, a single short strip, lattices of
-    2 and 3 columns or 2 rows -- equals the tile form bit for bit over 5
-    steps, for several segment lengths."""
+    """The paired marching form (two columns per lane, 124-column strips) on
+    ragged lattices -- the last strip 2 to 124 columns wide, a single strip
+    narrower than the wavefront's lanes, lattices of 2 and 4 columns or of 2
+    rows, one or two whole strips -- equals the tile form bit for bit
+    over 5 steps, for several segment lengths."""
     nx, ny = shape
     e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=nx + ny)
     # the driven shell 2 <= |k| <= 5, narrowed to stay below the Nyquist wave
-    # number of the 9-row lattice
+    # number of the smallest lattices
     fr = rl.Forcing(1e-4, 2.0, min(5.0, min(nx, ny) // 2 - 1), 3) if forced else None
 
     def run(kind, param):
@@ -631,6 +633,18 @@ def test_paired_form_is_bitwise_equal_to_tile_form(storage, shape, cfl, forced):
     ref = run("tile", 4)
     for param in (0, 1, 3, 16, 500):
         assert np.array_equal(run("march_pairs", param), ref), param
+
+
+@pytest.mark.parametrize("nx", [3, 37, 129])
+def test_paired_form_rejected_for_odd_nx(nx):
+    """A pair of columns never straddles the periodic wrap: odd nx is refused
+    (EUNSUPPORTED), and the autotuner passes over the form."""
+    lat = rl.Lattice(nx, 8, 0.6, storage="F16S")
+    with pytest.raises(rl.RlbmError) as ex:
+        lat.set_kernel("march_pairs", 0)
+    assert ex.value.code == rl.EUNSUPPORTED
+    kind, _ = lat.autotune(2)
+    assert kind != "march_pairs"
 
 
 def test_paired_form_rejected_for_32_and_64_bit_storage():
