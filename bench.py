@@ -24,6 +24,9 @@ The JSON line carries, beside the headline:
   * "forced512": the 512^2 workload, whose buffers fit the Infinity Cache
     (effective GB/s only, not an HBM figure);
   * "ensemble256": the 256-lattice ensemble in one persistent launch per step;
+  * "insitu": the 8192^2 and 2048^2 FP32 runs with their in-situ diagnostics
+    (energy spectrum and enstrophy every 500 / 1000 steps), MLUPS including
+    the diagnostics;
   * "copy": the library's streaming copy of one FP32 step's bytes (the
     practical HBM ceiling) and torch's device copy;
   * "roofline": algorithmic bytes per launch of the step kernel the
@@ -279,6 +282,43 @@ def workload_forms(rl, torch, wl, keys, steps, warmup, chunk, prof_n, tune_steps
     if "F64" in out:
         for r in out.values():
             r["gain_vs_gpu_f64"] = r["mlups"] / out["F64"]["mlups"]
+    return out
+
+
+def run_insitu(rl, torch, wl, storage, form, every, cycles, nbins=None):
+    """The workload's run with its in-situ diagnostics: the energy spectrum and
+    enstrophy every `every` steps (Sec. IV / Sec. V), `cycles` times, in the
+    given kernel form; wall time of steps plus diagnostics (the spectrum call
+    synchronises), against the steps alone."""
+    lat = make_lattice(rl, wl, storage, torch)
+    lat.set_kernel(*form)
+    nb = nbins or wl.n // 2
+    lat.step(every)                          # warm-up, and the spectrum's scratch
+    lat.spectrum(nb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        lat.step(every)
+        Ek, Z = lat.spectrum(nb)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        lat.step(every)
+    torch.cuda.synchronize()
+    steps_only = time.perf_counter() - t0
+    sites = wl.n * wl.n
+    out = {"storage": storage, "kernel_form": list(form), "steps_between_diagnostics": every,
+           "cycles": cycles, "bins": nb,
+           "ms_per_step_with_diagnostics": 1e3 * wall / (cycles * every),
+           "ms_per_step_steps_only": 1e3 * steps_only / (cycles * every),
+           "diagnostic_ms": 1e3 * (wall - steps_only) / cycles,
+           "mlups_with_diagnostics": sites * cycles * every / wall / 1e6,
+           "enstrophy_last": Z, "energy_last": float(np.sum(Ek)),
+           "unstable": lat.check() != rl.OK}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
     return out
 
 
@@ -543,6 +583,15 @@ def main():
         extra["ensemble256"] = run_ensemble(rl, torch, 200, 20)
         log(f"ensemble256 F32: {extra['ensemble256']['mlups']:.0f} MLUPS")
         torch.cuda.empty_cache()
+        # the configurations' diagnostics cadence: 8192^2 spectrum and enstrophy
+        # every 500 steps, 2048^2 spectrum every 1000 steps
+        extra["insitu"] = {
+            "forced8192": run_insitu(rl, torch, wl, "F32", tuple(head["kernel_form"]), 500, 2),
+            "forced2048": run_insitu(rl, torch, w2, "F32", tuple(f2["F32"]["kernel_form"]), 1000, 2),
+        }
+        for k, v in extra["insitu"].items():
+            log(f"{k} F32 with diagnostics every {v['steps_between_diagnostics']} steps: "
+                f"{v['mlups_with_diagnostics']:.0f} MLUPS, diagnostic {v['diagnostic_ms']:.1f} ms")
 
     cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_rows)
     if cpu:

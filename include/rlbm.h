@@ -264,8 +264,8 @@ int rlbm_load(rlbm_ctx* ctx, const void* h_buf, size_t bytes);
 
 /* Streaming copy of `bytes` bytes from d_src to d_dst on hip_stream (NULL:
  * the null stream), `reps` times after one untimed copy, with 16-byte loads
- * and stores and four loads in flight per thread over a persistent grid of 8
- * blocks per compute unit.  *h_ms receives the mean duration of one copy in
+ * and stores and four loads in flight per thread, 8 blocks per compute unit,
+ * each copying one contiguous chunk.  *h_ms receives the mean duration of one copy in
  * milliseconds (HIP events around the reps; synchronises).  A copy moves
  * 2 * bytes through HBM when both buffers are larger than the caches: the
  * practical streaming ceiling against which the step's bandwidth is read.

@@ -214,8 +214,9 @@ struct Engine {
     // form, J terms each).
     size_t lds_bytes(int kind) const {
         if (storage == RLBM_F64 || !any_forced) return 0;
-        const size_t cols = kind == kKernelMarchPair ? 2 * kTileW
-                            : (kind == kKernelMarch || kind == kKernelMarch2) ? kTileW : 0;
+        const size_t cols = kind == kKernelMarch2 ? 4 * kTileW
+                            : kind == kKernelMarchPair ? 2 * kTileW
+                            : kind == kKernelMarch ? kTileW : 0;
         return cols * (size_t)maxJ * sizeof(float);
     }
     // The marching forms hold at most kMaxMarchJ force terms per row in
@@ -281,7 +282,8 @@ struct Engine {
     // their maps, the persistent grid
     int configure_map(int m) {
         Cfg& c = cfg[m];
-        if (c.kind != kKernelTile) c.th = 4;          // 4 wavefronts per block (kStageTH)
+        // 4 wavefronts per block (kStageTH), 8 for the two-step form
+        if (c.kind != kKernelTile) c.th = c.kind == kKernelMarch2 ? 8 : 4;
         const int per_cu = occupancy(c.kind, c.th);
         const int slots = cus * per_cu;
         const int width = c.kind == kKernelMarch2 ? kTileW - 2
@@ -324,9 +326,13 @@ struct Engine {
             // padded to a multiple of the block's four wavefronts (which share
             // the strip's force basis)
             if (!tiled) w.tiles_y = (w.tiles_y + 3) & ~3;
+            // the two-step form takes strips in fours (and segments in pairs)
+            const int work = c.kind == kKernelMarch2
+                                 ? 8 * ((w.tiles_x + 3) / 4) * (((d.ny + w.seglen - 1) / w.seglen + 1) / 2)
+                                 : w.tiles_x * w.tiles_y;
             w.tile_begin = c.n_tiles;
-            c.n_tiles += w.tiles_x * w.tiles_y;
-            if (n_real > 1) map.insert(map.end(), (size_t)w.tiles_x * w.tiles_y, (uint16_t)r);
+            c.n_tiles += work;
+            if (n_real > 1) map.insert(map.end(), (size_t)work, (uint16_t)r);
             w.gitem_begin = c.n_gitems;
             const int items = d.K >= 0 ? (d.K + 1) * ((d.ny + rows - 1) / rows) : 0;
             c.n_gitems += items;
@@ -338,7 +344,7 @@ struct Engine {
         if (n_real > 1 && !gmap.empty())
             HIPCHK(hipMemcpyAsync(c.d_gitems, gmap.data(), sizeof(uint16_t) * gmap.size(),
                                   hipMemcpyHostToDevice, stream));
-        const int groups = tiled ? c.n_tiles : (c.n_tiles + 3) / 4;
+        const int groups = tiled ? c.n_tiles : (c.n_tiles + c.th - 1) / c.th;
         c.tile_blocks = std::max(8, std::min(groups, slots));
         // when the tiles leave resident slots free, build the next force tables
         // on extra blocks that run alongside the tiles

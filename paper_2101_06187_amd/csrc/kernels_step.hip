@@ -185,6 +185,23 @@ struct MarchItem {
         ya = seg * seglen;
         yb = min(ny, ya + seglen);
     }
+    // The two-step form: a block's eight wavefronts take four adjacent strips
+    // x two consecutive segments (strip 4 p + (w & 3), segment 2 b + (w >> 2)),
+    // so that the wavefronts marching side by side on one compute unit share
+    // the cache lines at their strips' common edges; the strip count is
+    // padded to a multiple of 4, the segment count of a strip to even
+    // (padding items have no rows).
+    __device__ void decode_quads(int local, int strips, int ny, int seglen) {
+        const int segs = (ny + seglen - 1) / seglen;
+        const int squads = (strips + 3) >> 2;
+        const int grp = local >> 3;
+        const int band = grp / squads;
+        strip = 4 * (grp - band * squads) + (local & 3);
+        seg = 2 * band + ((local >> 2) & 1);
+        rows = seg < segs && strip < strips;
+        ya = seg * seglen;
+        yb = min(ny, ya + seglen);
+    }
 };
 
 template <class S, class St, int SM, bool FORCED>
@@ -1260,7 +1277,7 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
 // update_site as every other form, so results are bitwise identical.
 // ---------------------------------------------------------------------------
 template <class S, class St, int SM, bool FORCED>
-__global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
+__global__ __launch_bounds__(512) void march2_kernel(StepArgs A) {
     static_assert(SM != kStreamHalo2, "the row-marching form streams from the nearest rows only");
     constexpr bool UNIT = SM == kStreamUnit;
     using T = typename S::T;
@@ -1283,19 +1300,19 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
     const int b = blockIdx.x;
     const int xcd = b & 7;
     const int nb = (G - xcd + 7) >> 3;
-    const int n_groups = (A.n_tiles + 3) >> 2;
+    const int n_groups = (A.n_tiles + 7) >> 3;
     const int chunk = (n_groups + 7) >> 3;
     const int g_end = min(n_groups, (xcd + 1) * chunk);
 
     // The loop over groups is uniform over the block (the basis barriers).
     for (int grp = b < G ? xcd * chunk + (b >> 3) : g_end; grp < g_end; grp += nb) {
-        const int u = grp * 4 + wv;
+        const int u = grp * 8 + wv;
         const int r = A.tile_real ? uni((int)A.tile_real[u]) : 0;
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
         MarchItem it;
-        it.decode(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
-                  uni(Dsc.wm[A.map].seglen));
+        it.decode_quads(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
+                        uni(Dsc.wm[A.map].seglen));
         const int ya = it.ya, yb = it.yb;
         const int x0 = it.strip * kOut;
         auto wrapx = [&](int v) { v %= nx; return v < 0 ? v + nx : v; };
@@ -1306,11 +1323,18 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             K = uni(Dsc.K);
             if constexpr (MF) J = uni(Dsc.J);
         }
+        // this wavefront's strip's columns in the block's force basis (the
+        // block's four strips side by side, 64 columns each)
+        const int bcol = lane + kTileW * (it.strip & 3);
         if constexpr (MF) {
-            // this strip's force basis, shared by the block's four wavefronts
-            __syncthreads();                      // the previous strip's readers are done
+            // the force basis of the block's four strips (positions 64 s + col:
+            // strip 4 p + s, column col), shared by its eight wavefronts
+            const int xp = (it.strip & ~3) * kOut;
+            __syncthreads();                      // the previous strips' readers are done
             if (K >= 0)
-                stage_basis(uni(Dsc.bas), J, kTileW, [&](int col) { return wrapx(x0 - 1 + col); });
+                stage_basis(uni(Dsc.bas), J, 4 * kTileW, [&](int pos) {
+                    return wrapx(xp + kOut * (pos >> 6) - 1 + (pos & 63));
+                });
             __syncthreads();
         }
         if (!it.rows) continue;
@@ -1399,7 +1423,7 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
         if constexpr (MF) {
             if (K >= 0) {
                 load_coefs(cf, rowA(r0), rowB(r0), nch, fl);
-                Fsum = force_sum_lds(cf, rowA(r0), rowB(r0), 2 * (K + 1), lane, kTileW, fl);
+                Fsum = force_sum_lds(cf, rowA(r0), rowB(r0), 2 * (K + 1), bcol, 4 * kTileW, fl);
             }
         }
         T cur[Q], up[M::nU], dn[M::nD];           // input rows rr, rr - 1, rr + 1
@@ -1539,7 +1563,7 @@ __global__ __launch_bounds__(256) void march2_kernel(StepArgs A) {
             });
             // the forces of the next iteration
             if constexpr (MF) {
-                if (K >= 0) Fsum = force_sum_lds(cf, rowA(rr + 1), rowB(rr + 1), 2 * (K + 1), lane, kTileW, fl);
+                if (K >= 0) Fsum = force_sum_lds(cf, rowA(rr + 1), rowB(rr + 1), 2 * (K + 1), bcol, 4 * kTileW, fl);
             }
         }
     }
