@@ -326,10 +326,20 @@ struct Engine {
             // padded to a multiple of the block's four wavefronts (which share
             // the strip's force basis)
             if (!tiled) w.tiles_y = (w.tiles_y + 3) & ~3;
-            // the two-step form takes strips in fours (and segments in pairs)
-            const int work = c.kind == kKernelMarch2
-                                 ? 8 * ((w.tiles_x + 3) / 4) * (((d.ny + w.seglen - 1) / w.seglen + 1) / 2)
-                                 : w.tiles_x * w.tiles_y;
+            // the two-step form: blocks of g adjacent strips x 8 / g segments,
+            // g = 4, 2 or 1, the largest that pads the strip count by at most
+            // 1/16 (wide lattices: 4; lattices of 2, 3 or 5 strips: 2 or 1)
+            w.group = 1;
+            int work = w.tiles_x * w.tiles_y;
+            if (c.kind == kKernelMarch2) {
+                for (int g : {4, 2}) {
+                    const int padded = (w.tiles_x + g - 1) / g * g;
+                    if (16 * (padded - w.tiles_x) <= w.tiles_x) { w.group = g; break; }
+                }
+                const int g = w.group, per = 8 / g;
+                const int segs = (d.ny + w.seglen - 1) / w.seglen;
+                work = 8 * ((w.tiles_x + g - 1) / g) * ((segs + per - 1) / per);
+            }
             w.tile_begin = c.n_tiles;
             c.n_tiles += work;
             if (n_real > 1) map.insert(map.end(), (size_t)work, (uint16_t)r);

@@ -21,6 +21,7 @@ struct WorkMap {
     int tile_begin;               // first work item (tile or strip segment) of this lattice
     int seglen;                   // rows per strip segment (marching kernels)
     int gitem_begin;              // first force-table work item of this lattice
+    int group;                    // two-step form: adjacent strips per block (1, 2 or 4)
 };
 
 // Per-lattice descriptor, resident in the workspace; every field is read

@@ -185,19 +185,21 @@ struct MarchItem {
         ya = seg * seglen;
         yb = min(ny, ya + seglen);
     }
-    // The two-step form: a block's eight wavefronts take four adjacent strips
-    // x two consecutive segments (strip 4 p + (w & 3), segment 2 b + (w >> 2)),
-    // so that the wavefronts marching side by side on one compute unit share
-    // the cache lines at their strips' common edges; the strip count is
-    // padded to a multiple of 4, the segment count of a strip to even
-    // (padding items have no rows).
-    __device__ void decode_quads(int local, int strips, int ny, int seglen) {
+    // The two-step form: a block's eight wavefronts take g adjacent strips x
+    // 8 / g consecutive segments (strip g p + w % g, segment (8 / g) b + w / g;
+    // g = 1, 2 or 4 per lattice), so that the wavefronts marching side by side
+    // on one compute unit share the cache lines at their strips' common
+    // edges; the strip count is padded to a multiple of g, the segment count
+    // of a strip to a multiple of 8 / g (padding items have no rows).
+    __device__ void decode_group(int local, int strips, int g, int ny, int seglen) {
         const int segs = (ny + seglen - 1) / seglen;
-        const int squads = (strips + 3) >> 2;
+        const int sgroups = (strips + g - 1) / g;
         const int grp = local >> 3;
-        const int band = grp / squads;
-        strip = 4 * (grp - band * squads) + (local & 3);
-        seg = 2 * band + ((local >> 2) & 1);
+        const int band = grp / sgroups;
+        const int w = local & 7;
+        const int gw = w / g;                     // g is 1, 2 or 4
+        strip = g * (grp - band * sgroups) + (w - gw * g);
+        seg = (8 / g) * band + gw;
         rows = seg < segs && strip < strips;
         ya = seg * seglen;
         yb = min(ny, ya + seglen);
@@ -1311,7 +1313,8 @@ __global__ __launch_bounds__(512) void march2_kernel(StepArgs A) {
         const RealDesc& Dsc = A.desc[r];
         const int nx = uni(Dsc.nx), ny = uni(Dsc.ny);
         MarchItem it;
-        it.decode_quads(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), ny,
+        const int g = uni(Dsc.wm[A.map].group);
+        it.decode_group(u - uni(Dsc.wm[A.map].tile_begin), uni(Dsc.wm[A.map].tiles_x), g, ny,
                         uni(Dsc.wm[A.map].seglen));
         const int ya = it.ya, yb = it.yb;
         const int x0 = it.strip * kOut;
@@ -1324,12 +1327,14 @@ __global__ __launch_bounds__(512) void march2_kernel(StepArgs A) {
             if constexpr (MF) J = uni(Dsc.J);
         }
         // this wavefront's strip's columns in the block's force basis (the
-        // block's four strips side by side, 64 columns each)
-        const int bcol = lane + kTileW * (it.strip & 3);
+        // block's g strips side by side, 64 columns each)
+        const int gs = it.strip - (it.strip / g) * g;
+        const int bcol = lane + kTileW * gs;
         if constexpr (MF) {
-            // the force basis of the block's four strips (positions 64 s + col:
-            // strip 4 p + s, column col), shared by its eight wavefronts
-            const int xp = (it.strip & ~3) * kOut;
+            // the force basis of the block's strips (positions 64 s + col:
+            // strip g p + s, column col; always four strips' positions, so
+            // that the LDS stride is a constant), shared by its eight wavefronts
+            const int xp = (it.strip - gs) * kOut;
             __syncthreads();                      // the previous strips' readers are done
             if (K >= 0)
                 stage_basis(uni(Dsc.bas), J, 4 * kTileW, [&](int pos) {
