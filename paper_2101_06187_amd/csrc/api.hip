@@ -327,18 +327,24 @@ struct Engine {
             // the strip's force basis)
             if (!tiled) w.tiles_y = (w.tiles_y + 3) & ~3;
             // the two-step form: blocks of g adjacent strips x 8 / g segments,
-            // g = 4, 2 or 1, the largest that pads the strip count by at most
-            // 1/16 (wide lattices: 4; lattices of 2, 3 or 5 strips: 2 or 1)
+            // g = 4, 2 or 1: the largest whose padding (strips to a multiple of
+            // g, segments to a multiple of 8 / g) adds at most 1/16 of the work
+            // items, else the one that pads least (wide lattices: 4; the
+            // ensemble's lattices of 2, 3 or 5 strips: 2 or 1)
             w.group = 1;
             int work = w.tiles_x * w.tiles_y;
             if (c.kind == kKernelMarch2) {
-                for (int g : {4, 2}) {
-                    const int padded = (w.tiles_x + g - 1) / g * g;
-                    if (16 * (padded - w.tiles_x) <= w.tiles_x) { w.group = g; break; }
-                }
-                const int g = w.group, per = 8 / g;
                 const int segs = (d.ny + w.seglen - 1) / w.seglen;
-                work = 8 * ((w.tiles_x + g - 1) / g) * ((segs + per - 1) / per);
+                auto items = [&](int g) {
+                    return (long long)8 * ((w.tiles_x + g - 1) / g) * ((segs + 8 / g - 1) / (8 / g));
+                };
+                const long long real = (long long)w.tiles_x * segs;
+                long long best = -1;
+                for (int g : {4, 2, 1}) {
+                    if (16 * (items(g) - real) <= real) { w.group = g; best = -1; break; }
+                    if (best < 0 || items(g) < best) { best = items(g); w.group = g; }
+                }
+                work = (int)items(w.group);
             }
             w.tile_begin = c.n_tiles;
             c.n_tiles += work;
