@@ -1088,15 +1088,20 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                 }
                 force_chunk2<decltype(all)::value>(FA, FB, a, bA, bB, n);
             };
-            const int tail = force_tail(jt);
+            // the chunk count and the last chunk's length pass through an
+            // empty asm statement, so that the compiler compares them here
+            // rather than keeping the comparisons' masks in scalar registers
+            // across the row loop (which spilled them)
+            int tail = force_tail(jt), nc = nch;
+            asm volatile("" : "+s"(tail), "+s"(nc));
 #pragma unroll
             for (int c = 0; c < kPairCoefs; ++c) {
-                if (c + 1 < nch) chunk(c, cf[c], std::true_type{}, kForceChunk);
-                else if (c + 1 == nch) chunk(c, cf[c], std::false_type{}, tail);
+                if (c + 1 < nc) chunk(c, cf[c], std::true_type{}, kForceChunk);
+                else if (c + 1 == nc) chunk(c, cf[c], std::false_type{}, tail);
             }
-            for (int c = kPairCoefs; c < nch; ++c)
+            for (int c = kPairCoefs; c < nc; ++c)
                 chunk(c, coef_row(yy)[kForceChunk * 2 * c + coef_off(yy)], std::false_type{},
-                      c + 1 < nch ? kForceChunk : tail);
+                      c + 1 < nc ? kForceChunk : tail);
         };
 
         if constexpr (FORCED) {
