@@ -94,6 +94,52 @@ def test_two_step_form_narrow_lattices(shape, forced):
         lat.close()
 
 
+@pytest.mark.parametrize("shape,param", [((62 * 8, 40), 4), ((62 * 8 + 3, 37), 3),
+                                         ((62 * 5, 24), 3), ((62 * 3 - 1, 50), 5),
+                                         ((62 * 2, 9), 2), ((62, 17), 0), ((62 * 9 + 1, 12), 1)])
+def test_two_step_form_strip_groups(shape, param):
+    """The two-step form's blocks of g adjacent strips x 8 / g segments (g =
+    4, 2 or 1, chosen from the padding of strips and segments): lattices of
+    1 to 10 strips, ragged last strips and segment counts that do not divide
+    into the block, FP32 with forcing, 6 steps (three launches) bitwise equal
+    to the tile form; then an ensemble of such lattices at once."""
+    nx, ny = shape
+    e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=nx + ny)
+    fr = rl.Forcing(1e-4, 1.0, min(4.0, ny // 2 - 1), 9)
+
+    def run(kind, p):
+        lat = rl.Lattice(nx, ny, 0.57, storage="F32", forcing=fr)
+        lat.set_kernel(kind, p)
+        lat.set_state(dev(e), dev(bx), dev(by))
+        lat.step(6)
+        assert lat.check() == rl.OK
+        out = host(lat.populations())
+        lat.close()
+        return out
+
+    assert np.array_equal(run("march2", param), run("tile", 4)), (shape, param)
+
+
+def test_two_step_form_strip_groups_in_an_ensemble():
+    sizes = [(62 * 8, 40), (124, 9), (62 * 3 - 1, 50), (64, 64), (200, 30)]
+    taus = [0.55, 0.6, 0.7, 0.8, 0.65]
+    frs = [rl.Forcing(1e-4, 1.0, 3.0, r) for r in range(len(sizes))]
+    out = []
+    for kind, param in (("tile", 4), ("march2", 3), ("march2", 0)):
+        ens = rl.Ensemble(sizes, taus, storage="F32", forcings=frs)
+        ens.set_kernel(kind, param)
+        for r, (nx, ny) in enumerate(sizes):
+            e, bx, by = workloads.noisy_rest(ny, nx, 0.01, seed=r)
+            ens.set_state(r, dev(e), dev(bx), dev(by))
+        ens.step(4)
+        assert ens.check() == rl.OK
+        out.append([host(ens.populations(r)) for r in range(len(sizes))])
+        ens.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
+
+
 def test_two_step_form_refused_below_three_rows():
     """ny = 2 is below what the two-step form reads: EUNSUPPORTED from the
     lattice and the ensemble; the autotuner leaves it out and keeps a form
