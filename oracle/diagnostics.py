@@ -13,6 +13,10 @@ spectrum    -- Sec. IV: E(k) is the kinetic energy per wave-number magnitude.
                average and a derivative): shell sum
                    E(k_b) = sum_{round(|k|) = k_b} 1/2 |beta_hat(k)|^2,
                beta_hat = DFT(beta) / (nx ny), integer k in [-n/2, n/2)^2.
+               The paper's spectral energy density, half the squared velocity
+               amplitude averaged over the directions of k, is on the lattice
+               the shell sum divided by the shell's number of wave vectors
+               (shell_modes).
                Enstrophy (Sec. IV, vorticity w = curl v):
                    Z = 1/2 sum_k |w_hat(k)|^2,
                    w_hat = i (2 pi kx / nx) beta_hat_y - i (2 pi ky / ny) beta_hat_x.
@@ -61,6 +65,17 @@ def spectrum(beta_x, beta_y, nbins):
     w = 1j * (2 * np.pi * KX / nx) * by - 1j * (2 * np.pi * KY / ny) * bx
     Z = 0.5 * (np.abs(w) ** 2).sum()
     return Ek, Z
+
+
+def shell_modes(nx, ny, nbins):
+    """Number of integer wave vectors k (DFT numbering, as in ``spectrum``)
+    with round(|k|) = b, for b = 0 .. nbins-1: dividing a shell sum by it
+    gives the average over the directions of k (Sec. IV)."""
+    kx = np.fft.fftfreq(nx, 1.0 / nx)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    KY, KX = np.meshgrid(ky, kx, indexing="ij")
+    shell = np.rint(np.sqrt(KX ** 2 + KY ** 2)).astype(np.int64).ravel()
+    return np.bincount(shell[shell < nbins], minlength=nbins)[:nbins]
 
 
 def filtered_velocity(beta_x, beta_y, k_lo, k_hi):

@@ -82,3 +82,49 @@ def test_spectrum_average_special_cases():
     _, e1 = diagnostics.spectrum_average(R)
     _, e2 = diagnostics.spectrum_average(3.0 * R[::-1])
     assert np.abs(e2 - 3.0 * e1).max() < 1e-14
+
+
+def _r2(n):
+    """Representations of n as a sum of two squares of integers (signs and
+    order counted), by Jacobi's two-square theorem: 4 (d_1(n) - d_3(n)),
+    d_r the number of divisors congruent to r mod 4; r2(0) = 1."""
+    if n == 0:
+        return 1
+    d = [q for q in range(1, n + 1) if n % q == 0]
+    return 4 * (sum(1 for q in d if q % 4 == 1) - sum(1 for q in d if q % 4 == 3))
+
+
+def test_shell_modes_by_the_two_square_theorem():
+    """A shell b inside the lattice's wave-number box holds the k with
+    (b - 1/2)^2 < |k|^2 < (b + 1/2)^2, i.e. |k|^2 = b^2 - b + 1 .. b^2 + b
+    (ties are impossible: |k|^2 is an integer), so its count is a sum of r2."""
+    for nx, ny in ((64, 64), (64, 32), (31, 33)):
+        nb = (min(nx, ny) - 1) // 2           # shells with b + 1/2 inside the box
+        got = diagnostics.shell_modes(nx, ny, nb)
+        expect = [1] + [sum(_r2(m) for m in range(b * b - b + 1, b * b + b + 1))
+                        for b in range(1, nb)]
+        np.testing.assert_array_equal(got, expect)
+    np.testing.assert_array_equal(diagnostics.shell_modes(64, 64, 5), [1, 8, 12, 16, 32])
+
+
+def test_shell_modes_count_every_wave_vector_once():
+    for nx, ny in ((16, 16), (16, 4), (5, 7), (1, 1), (2, 1), (1, 9)):
+        nb = int(np.ceil(np.hypot(nx / 2, ny / 2))) + 2
+        c = diagnostics.shell_modes(nx, ny, nb)
+        assert c.sum() == nx * ny and c[-1] == 0
+    # fewer bins: the higher shells are left out, the lower ones unchanged
+    np.testing.assert_array_equal(diagnostics.shell_modes(16, 16, 4),
+                                  diagnostics.shell_modes(16, 16, 20)[:4])
+
+
+def test_angular_average_of_a_point_impulse_is_flat():
+    """beta_x = nx ny delta(x) has beta_hat = 1 at every k, so each shell sum
+    of the spectrum is 1/2 times the shell's number of wave vectors: the
+    angular average (Sec. IV) is 1/2 in every shell."""
+    nx, ny = 32, 16
+    bx = np.zeros((ny, nx))
+    bx[0, 0] = nx * ny
+    Ek, _ = diagnostics.spectrum(bx, np.zeros_like(bx), 20)
+    c = diagnostics.shell_modes(nx, ny, 20)
+    np.testing.assert_allclose(Ek[c > 0] / c[c > 0], 0.5, rtol=1e-14)
+    assert np.all(Ek[c == 0] == 0)
