@@ -238,6 +238,17 @@ int rlbm_filtered_velocity(rlbm_ctx* ctx, void* d_scratch, size_t scratch_bytes,
                            double k_lo, double k_hi, double* d_ux, double* d_uy,
                            double* h_mean_speed);
 
+/* Number of integer wave vectors in each shell of rlbm_spectrum:
+ *   h_counts[b] = #{ k : round(|k|) = b },  b = 0 .. nbins-1,
+ * k running over the DFT's integer wave numbers of an nx x ny lattice (per
+ * axis k = i for 2i < n, else i - n: [-n/2, n/2) for even n).  Sec. IV
+ * defines the spectral energy density as half the squared velocity amplitude
+ * averaged over the directions of k; on the lattice that average is the
+ * shell sum E(k_b) of rlbm_spectrum divided by h_counts[b].  Any nx, ny >= 1.
+ * Pure host function (integer arithmetic, work of order ny times the shells
+ * a row crosses).  EINVAL for nx, ny or nbins < 1 or a NULL h_counts.       */
+int rlbm_shell_modes(int32_t nx, int32_t ny, int32_t nbins, int64_t* h_counts);
+
 /* Time-averaged spectrum and its error estimate (the paper's appendix on the
  * minimum simulation time): from M spectra sampled every N steps, N being a
  * decorrelation interval,

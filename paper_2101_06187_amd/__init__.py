@@ -85,6 +85,7 @@ SIGNATURES = [
     ("rlbm_spectrum_static", _I, [_P, _P, _I32, _P]),
     ("rlbm_filtered_velocity", _I, [_P, _P, _SZ, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     ("rlbm_spectrum_average", _I, [_P, _I32, _I32, _P, _P]),
+    ("rlbm_shell_modes", _I, [_I32, _I32, _I32, _P]),
     ("rlbm_state_bytes", _I, [_P, _P]),
     ("rlbm_save", _I, [_P, _P, _SZ]),
     ("rlbm_load", _I, [_P, _P, _SZ]),
@@ -201,6 +202,14 @@ def stream_copy(src, dst, reps=10):
     _check(lib().rlbm_stream_copy(_ptr(src), _ptr(dst), nbytes, int(reps), _stream(src.device),
                                   ctypes.byref(ms)))
     return ms.value
+
+
+def shell_modes(nx, ny, nbins):
+    """Number of integer wave vectors in each shell of Lattice.spectrum; the
+    shell sum divided by it is the average over the directions of k."""
+    out = np.zeros(int(nbins), dtype=np.int64)
+    _check(lib().rlbm_shell_modes(int(nx), int(ny), int(nbins), out.ctypes.data_as(_P)))
+    return out
 
 
 def spectrum_average(samples):

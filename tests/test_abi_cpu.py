@@ -161,3 +161,17 @@ def test_spectrum_average_matches_oracle():
     assert np.abs(err - oe).max() <= 1e-14 * np.abs(oe).max()
     with pytest.raises(rl.RlbmError):
         rl.spectrum_average(np.zeros((0, 3)))
+
+
+def test_shell_modes_match_oracle():
+    from oracle import diagnostics
+    for nx, ny, nb in ((64, 64, 50), (64, 64, 7), (16, 4, 14), (5, 7, 8), (1, 1, 3), (2, 1, 4),
+                       (128, 32, 100), (1, 9, 6), (256, 2, 130), (1024, 1024, 724)):
+        np.testing.assert_array_equal(rl.shell_modes(nx, ny, nb),
+                                      diagnostics.shell_modes(nx, ny, nb), err_msg=f"{nx}x{ny}")
+    assert rl.shell_modes(8192, 8192, 5794).sum() == 8192 * 8192   # corner |k| = 5792.6
+    L = rl.lib()
+    out = np.zeros(4, dtype=np.int64)
+    for args in ((0, 4, 4), (4, 0, 4), (4, 4, 0)):
+        assert L.rlbm_shell_modes(*args, out.ctypes.data_as(rl._P)) == rl.EINVAL
+    assert L.rlbm_shell_modes(4, 4, 4, None) == rl.EINVAL
