@@ -206,8 +206,15 @@ struct MarchItem {
     }
 };
 
+// The tile form.  With 16-bit storage at cfl = 1 it is held to five
+// wavefronts per SIMD (96 VGPRs): its blocks are 64 x th lanes, so residency
+// moves in single wavefronts.
+template <class S, int SM>
+constexpr int tile_min_waves() { return sizeof(typename S::raw) == 2 && SM == kStreamUnit ? 5 : 1; }
+
 template <class S, class St, int SM, bool FORCED>
-__global__ __launch_bounds__(512) void step_kernel(StepArgs A) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(tile_min_waves<S, SM>())))
+void step_kernel(StepArgs A) {
     using T = typename S::T;
     using raw = typename S::raw;
     constexpr int D = St::D;
@@ -566,7 +573,7 @@ __global__ __launch_bounds__(64 * kStageTH, stage_min_waves<S>()) void staged_ke
         }
         if (lx <= R && y < ny) {
             T f[Q];
-            stream_interp<St, SM>(
+            stream_interp<St, SM, mix_interp<S>>(
                 [&](int q, int j, int i) -> T {
                     return (T)S::ld(&sm[M::srow(w + j, q) * kLdsW + 3 + lx + i]);
                 },
@@ -843,7 +850,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
                     f[q] = own;
                 } else if constexpr (d.cx == 0) {
                     if constexpr (UNIT && n == 1) f[q] = vert;
-                    else f[q] = lerp(own, vert, W.a[n - 1]);
+                    else f[q] = lerp<mix_interp<S>>(own, vert, W.a[n - 1]);
                 } else {
                     // x-neighbour upstream: lane - 1 for c_x > 0, lane + 1 for c_x < 0,
                     // by a wave shift; the edge lane takes the halo column -- lane 0,
@@ -859,13 +866,12 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs A) {
                     const T own_nb = shifted(own, h_own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = own_nb;
-                        else f[q] = lerp(own, own_nb, W.a[n - 1]);
+                        else f[q] = lerp<mix_interp<S>>(own, own_nb, W.a[n - 1]);
                     } else {
                         // halo of the upstream row: y-1 (in hp) or y+1 (in hc)
                         const T h_vert = read_lane(d.cy > 0 ? hp : hc, H);
                         const T vert_nb = shifted(vert, h_vert);
-                        f[q] = fma(W.w11[n - 1], vert_nb,
-                                   fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                        f[q] = bilerp<mix_interp<S>>(own, own_nb, vert, vert_nb, W, n - 1);
                     }
                 }
             });
@@ -1157,7 +1163,7 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     f[q] = oa;
                 } else if constexpr (d.cx == 0) {
                     if constexpr (UNIT && n == 1) f[q] = va;
-                    else f[q] = lerp(oa, va, W.a[n - 1]);
+                    else f[q] = lerp<mix_interp<S>>(oa, va, W.a[n - 1]);
                 } else {
                     // left neighbour of column A: lane l - 1's high half, for
                     // lane 0 the halo
@@ -1167,13 +1173,13 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     else na = S::hi(own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = na;
-                        else f[q] = lerp(oa, na, W.a[n - 1]);
+                        else f[q] = lerp<mix_interp<S>>(oa, na, W.a[n - 1]);
                     } else {
                         // the upstream row's: y - 1 or y + 1
                         T vna;
                         if constexpr (d.cx > 0) vna = S::hi(from_left(vert, halo_bits(d.cy > 0 ? hm : h1, H) << 16));
                         else vna = S::hi(vert);
-                        f[q] = fma(W.w11[n - 1], vna, fma(W.w10[n - 1], na + va, W.w00[n - 1] * oa));
+                        f[q] = bilerp<mix_interp<S>>(oa, na, va, vna, W, n - 1);
                     }
                 }
             });
@@ -1202,7 +1208,7 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     f[q] = ob;
                 } else if constexpr (d.cx == 0) {
                     if constexpr (UNIT && n == 1) f[q] = vb;
-                    else f[q] = lerp(ob, vb, W.a[n - 1]);
+                    else f[q] = lerp<mix_interp<S>>(ob, vb, W.a[n - 1]);
                 } else {
                     // right neighbour of column B: lane l + 1's low half, for
                     // lane 63 the halo
@@ -1212,12 +1218,12 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     else nbv = S::lo(own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = nbv;
-                        else f[q] = lerp(ob, nbv, W.a[n - 1]);
+                        else f[q] = lerp<mix_interp<S>>(ob, nbv, W.a[n - 1]);
                     } else {
                         T vnb;
                         if constexpr (d.cx < 0) vnb = S::lo(from_right(vert, halo_bits(d.cy > 0 ? hm : h1, H)));
                         else vnb = S::lo(vert);
-                        f[q] = fma(W.w11[n - 1], vnb, fma(W.w10[n - 1], nbv + vb, W.w00[n - 1] * ob));
+                        f[q] = bilerp<mix_interp<S>>(ob, nbv, vb, vnb, W, n - 1);
                     }
                 }
             });
@@ -1469,17 +1475,16 @@ __global__ __launch_bounds__(512) void march2_kernel(StepArgs A) {
                         g[q] = own;
                     } else if constexpr (d.cx == 0) {
                         if constexpr (UNIT && n == 1) g[q] = vert;
-                        else g[q] = lerp(own, vert, W.a[n - 1]);
+                        else g[q] = lerp<mix_interp<S>>(own, vert, W.a[n - 1]);
                     } else {
                         // lanes 1 .. 62 need no halo (edge lanes are not stored)
                         const T own_nb = lane_shift<d.cx>(own, own);
                         if constexpr (d.cy == 0) {
                             if constexpr (UNIT && n == 1) g[q] = own_nb;
-                            else g[q] = lerp(own, own_nb, W.a[n - 1]);
+                            else g[q] = lerp<mix_interp<S>>(own, own_nb, W.a[n - 1]);
                         } else {
                             const T vert_nb = lane_shift<d.cx>(vert, vert);
-                            g[q] = fma(W.w11[n - 1], vert_nb,
-                                       fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                            g[q] = bilerp<mix_interp<S>>(own, own_nb, vert, vert_nb, W, n - 1);
                         }
                     }
                 });
@@ -1510,7 +1515,7 @@ __global__ __launch_bounds__(512) void march2_kernel(StepArgs A) {
                     f[q] = own;
                 } else if constexpr (d.cx == 0) {
                     if constexpr (UNIT && n == 1) f[q] = vert;
-                    else f[q] = lerp(own, vert, W.a[n - 1]);
+                    else f[q] = lerp<mix_interp<S>>(own, vert, W.a[n - 1]);
                 } else {
                     // the edge lane (0 or 63) takes the strip's halo column
                     constexpr int H = M::hidx(q);
@@ -1518,12 +1523,11 @@ __global__ __launch_bounds__(512) void march2_kernel(StepArgs A) {
                     const T own_nb = lane_shift<d.cx>(own, h_own);
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = own_nb;
-                        else f[q] = lerp(own, own_nb, W.a[n - 1]);
+                        else f[q] = lerp<mix_interp<S>>(own, own_nb, W.a[n - 1]);
                     } else {
                         const T h_vert = read_lane(d.cy > 0 ? hp : hc, H);
                         const T vert_nb = lane_shift<d.cx>(vert, h_vert);
-                        f[q] = fma(W.w11[n - 1], vert_nb,
-                                   fma(W.w10[n - 1], own_nb + vert, W.w00[n - 1] * own));
+                        f[q] = bilerp<mix_interp<S>>(own, own_nb, vert, vert_nb, W, n - 1);
                     }
                 }
             });

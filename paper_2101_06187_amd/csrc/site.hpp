@@ -172,8 +172,20 @@ struct StBF16S {
 // for c_x, c_y both non-zero (|v_x| = |v_y|) the bilinear weights are
 // (1 - a)^2 (own node), a (1 - a) (each edge neighbour), a^2 (diagonal).
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ T lerp(T p, T q, T t) { return fma(t, q - p, p); }
+// Interpolation formulas.  MIX (16-bit storage): every node value is an
+// operand of a fused multiply-add, which then takes the 16-bit value as it is
+// (v_fma_mix_f32) instead of after a conversion and an addition or
+// subtraction.  Otherwise (FP32, FP64 storage) the sums of node values are
+// formed first.  Every kernel form uses the same formula for a storage type.
+template <class S>
+constexpr bool mix_interp = sizeof(typename S::raw) == 2;
+
+// (1 - t) p + t q
+template <bool MIX, class T>
+__device__ __forceinline__ T lerp(T p, T q, T t) {
+    if constexpr (MIX) return fma(t, q, fma(-t, p, p));
+    else return fma(t, q - p, p);
+}
 
 template <class T>
 struct InterpW {
@@ -191,9 +203,18 @@ struct InterpW {
     }
 };
 
+// Bilinear interpolation with weights of W for i + 1 non-zero components:
+// o own node, h its upstream neighbour in the row, v in the column, dg the
+// diagonal one.
+template <bool MIX, class T>
+__device__ __forceinline__ T bilerp(T o, T h, T v, T dg, const InterpW<T>& W, int i) {
+    if constexpr (MIX) return fma(W.w11[i], dg, fma(W.w10[i], h, fma(W.w10[i], v, W.w00[i] * o)));
+    else return fma(W.w11[i], dg, fma(W.w10[i], h + v, W.w00[i] * o));
+}
+
 // The interpolation itself, for any source of the 3 x 3 neighbourhood:
 // ld(q, j, i) returns population q at row y + j - 1, column x + i - 1.
-template <class St, int SM, class T, class Ld>
+template <class St, int SM, bool MIX, class T, class Ld>
 __device__ __forceinline__ void stream_interp(Ld&& ld, const InterpW<T>& W, T (&f)[St::Q]) {
     constexpr bool UNIT = SM == kStreamUnit;
     sfor<0, St::Q>([&](auto iq) {
@@ -207,13 +228,14 @@ __device__ __forceinline__ void stream_interp(Ld&& ld, const InterpW<T>& W, T (&
             f[q] = L(1, 1);
         } else if constexpr (d.cy == 0) {
             if constexpr (UNIT && n == 1) f[q] = L(1, ux);
-            else f[q] = lerp(L(1, 1), L(1, ux), W.a[n - 1]);
+            else f[q] = lerp<MIX>(L(1, 1), L(1, ux), W.a[n - 1]);
         } else if constexpr (d.cx == 0) {
             if constexpr (UNIT && n == 1) f[q] = L(uy, 1);
-            else f[q] = lerp(L(1, 1), L(uy, 1), W.a[n - 1]);
+            else f[q] = lerp<MIX>(L(1, 1), L(uy, 1), W.a[n - 1]);
         } else {
-            const T s = L(1, ux) + L(uy, 1);
-            f[q] = fma(W.w11[n - 1], L(uy, ux), fma(W.w10[n - 1], s, W.w00[n - 1] * L(1, 1)));
+            const T h = L(1, ux), v = L(uy, 1);
+            const T dg = L(uy, ux);
+            f[q] = bilerp<MIX>(L(1, 1), h, v, dg, W, n - 1);
         }
     });
 }
@@ -226,7 +248,7 @@ __device__ __forceinline__ void stream_pull(const char* const (&rows)[3],
                                             T (&f)[St::Q]) {
     using raw = typename S::raw;
     constexpr long long plane_bytes = kTileW * sizeof(raw);
-    stream_interp<St, SM>(
+    stream_interp<St, SM, mix_interp<S>>(
         [&](int q, int j, int i) -> T {
             return (T)S::ld((gp<const raw>)(rows[j] + (long long)q * plane_bytes + cols[i]));
         },
