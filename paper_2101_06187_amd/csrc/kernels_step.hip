@@ -1113,12 +1113,22 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
         if constexpr (FORCED) {
             if (K >= 0) load_row_coefs(ya);
         }
-        uint32_t cur[Q], pre[Q], up[M::nU], dn[M::nD];
+        // The row window in three buffers whose roles rotate from row to row
+        // (the row loop is unrolled three times, so the window never moves
+        // between registers).  For a row y processed with buffers (X, Y, Z):
+        //   c_y >= 0: X = row y - 1 (c_y > 0), Y = row y, Z <- row y + 1;
+        //   c_y < 0:  X = row y, Y = row y + 1, Z <- row y + 2;
+        // row y + 1 is processed with (Y, Z, X).
+        uint32_t B0[Q], B1[Q], B2[Q];
         sfor<0, Q>([&](auto iq) {
             constexpr int q = decltype(iq)::value;
-            cur[q] = ld(q, ya);
-            if constexpr (M::cy(q) > 0) up[M::uidx(q)] = ld(q, ya - 1);
-            if constexpr (M::cy(q) < 0) dn[M::didx(q)] = ld(q, ya + 1);
+            if constexpr (M::cy(q) < 0) {
+                B0[q] = ld(q, ya);
+                B1[q] = ld(q, ya + 1);
+            } else {
+                if constexpr (M::cy(q) > 0) B0[q] = ld(q, ya - 1);
+                B1[q] = ld(q, ya);
+            }
         });
         // halo rows y - 1, y, y + 1 and (in flight) y + 2
         uint32_t hm = gather(ya - 1);
@@ -1126,7 +1136,8 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
         uint32_t h1 = gather(ya + 1);
         uint32_t h2 = 0;
 
-        for (int y = ya; y < yb; ++y) {
+        auto row = [&](int y, uint32_t (&X)[Q], uint32_t (&Y)[Q], uint32_t (&Z)[Q])
+                       __attribute__((always_inline)) {
             const bool even = ((y - ya) & 1) == 0;
             // the coefficients of rows y + 1, y + 2, ahead of this row's loads
             if constexpr (FORCED) {
@@ -1137,7 +1148,7 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
             // that the compiler's waits can leave these loads in flight
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
-                pre[q] = ld(q, M::cy(q) < 0 ? min(y + 2, yb) : min(y + 1, yb - 1));
+                Z[q] = ld(q, M::cy(q) < 0 ? min(y + 2, yb) : min(y + 1, yb - 1));
             });
             h2 = gather(min(y + 2, yb));
             // the forces of rows y, y + 1 (coefficients loaded an iteration ago)
@@ -1154,10 +1165,10 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                 constexpr int q = decltype(iq)::value;
                 constexpr Dir d = St::dir[q];
                 constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
-                const uint32_t own = cur[q];
+                const uint32_t own = d.cy < 0 ? X[q] : Y[q];
                 uint32_t vert = own;
-                if constexpr (d.cy > 0) vert = up[M::uidx(q)];
-                if constexpr (d.cy < 0) vert = dn[M::didx(q)];
+                if constexpr (d.cy > 0) vert = X[q];
+                if constexpr (d.cy < 0) vert = Y[q];
                 const T oa = S::lo(own), va = S::lo(vert);
                 if constexpr (d.cx == 0 && d.cy == 0) {
                     f[q] = oa;
@@ -1190,19 +1201,18 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
             // column B converts the window's halves anew: values kept from column
             // A's pass would stay live through A's update and cost registers
 #pragma unroll
-            for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(cur[i]));
-#pragma unroll
-            for (int i = 0; i < M::nU; ++i) asm volatile("" : "+v"(up[i]));
-#pragma unroll
-            for (int i = 0; i < M::nD; ++i) asm volatile("" : "+v"(dn[i]));
+            for (int i = 0; i < Q; ++i) {
+                if (M::cy(i) != 0) asm volatile("" : "+v"(X[i]));
+                asm volatile("" : "+v"(Y[i]));
+            }
             sfor<0, Q>([&](auto iq) {
                 constexpr int q = decltype(iq)::value;
                 constexpr Dir d = St::dir[q];
                 constexpr int n = (d.cx != 0) + (d.cy != 0) + (d.cz != 0);
-                const uint32_t own = cur[q];
+                const uint32_t own = d.cy < 0 ? X[q] : Y[q];
                 uint32_t vert = own;
-                if constexpr (d.cy > 0) vert = up[M::uidx(q)];
-                if constexpr (d.cy < 0) vert = dn[M::didx(q)];
+                if constexpr (d.cy > 0) vert = X[q];
+                if constexpr (d.cy < 0) vert = Y[q];
                 const T ob = S::hi(own), vb = S::hi(vert);
                 if constexpr (d.cx == 0 && d.cy == 0) {
                     f[q] = ob;
@@ -1247,22 +1257,16 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     __builtin_nontemporal_store(outp[q], (gp<uint32_t>)(drow + (long long)q * plane_bytes + colb));
                 });
             }
-            // roll the window
-            sfor<0, Q>([&](auto iq) {
-                constexpr int q = decltype(iq)::value;
-                if constexpr (M::cy(q) > 0) {
-                    up[M::uidx(q)] = cur[q];
-                    cur[q] = pre[q];
-                } else if constexpr (M::cy(q) < 0) {
-                    cur[q] = dn[M::didx(q)];
-                    dn[M::didx(q)] = pre[q];
-                } else {
-                    cur[q] = pre[q];
-                }
-            });
             hm = h0;
             h0 = h1;
             h1 = h2;
+        };
+        for (int y = ya; y < yb; y += 3) {
+            row(y, B0, B1, B2);
+            if (y + 1 >= yb) break;
+            row(y + 1, B1, B2, B0);
+            if (y + 2 >= yb) break;
+            row(y + 2, B2, B0, B1);
         }
     }
 
