@@ -1136,7 +1136,23 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
         uint32_t h1 = gather(ya + 1);
         uint32_t h2 = 0;
 
-        auto row = [&](int y, uint32_t (&X)[Q], uint32_t (&Y)[Q], uint32_t (&Z)[Q])
+        // Lane-shifted words of populations with c_x != 0 and c_y != 0 serve
+        // two rows: the shift of row y is the streamed neighbour of row y and
+        // the upstream neighbour of row y + 1 (c_y > 0), or that of row y - 1
+        // and of row y (c_y < 0).  They rotate with the window: for row y with
+        // shift buffers (SX, SY, SZ), SX holds the shift made one row earlier
+        // and SY receives this row's.
+        uint32_t T0[Q], T1[Q], T2[Q];
+        sfor<0, Q>([&](auto iq) {
+            constexpr int q = decltype(iq)::value;
+            constexpr int H = M::hidx(q);
+            if constexpr (M::cx(q) > 0 && M::cy(q) != 0)
+                T0[q] = from_left(B0[q], halo_bits(M::cy(q) > 0 ? hm : h0, H) << 16);
+            if constexpr (M::cx(q) < 0 && M::cy(q) != 0)
+                T0[q] = from_right(B0[q], halo_bits(M::cy(q) > 0 ? hm : h0, H));
+        });
+        auto row = [&](int y, uint32_t (&X)[Q], uint32_t (&Y)[Q], uint32_t (&Z)[Q],
+                       uint32_t (&SX)[Q], uint32_t (&SY)[Q], uint32_t (&SZ)[Q])
                        __attribute__((always_inline)) {
             const bool even = ((y - ya) & 1) == 0;
             // the coefficients of rows y + 1, y + 2, ahead of this row's loads
@@ -1180,16 +1196,25 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     // lane 0 the halo
                     constexpr int H = M::hidx(q);
                     T na;
-                    if constexpr (d.cx > 0) na = S::hi(from_left(own, halo_bits(h0, H) << 16));
-                    else na = S::hi(own);
+                    if constexpr (d.cx > 0) {
+                        if constexpr (d.cy > 0) na = S::hi(SY[q] = from_left(own, halo_bits(h0, H) << 16));
+                        else if constexpr (d.cy < 0) na = S::hi(SX[q]);
+                        else na = S::hi(from_left(own, halo_bits(h0, H) << 16));
+                    } else {
+                        na = S::hi(own);
+                    }
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = na;
                         else f[q] = lerp<mix_interp<S>>(oa, na, W.a[n - 1]);
                     } else {
                         // the upstream row's: y - 1 or y + 1
                         T vna;
-                        if constexpr (d.cx > 0) vna = S::hi(from_left(vert, halo_bits(d.cy > 0 ? hm : h1, H) << 16));
-                        else vna = S::hi(vert);
+                        if constexpr (d.cx > 0) {
+                            if constexpr (d.cy > 0) vna = S::hi(SX[q]);
+                            else vna = S::hi(SY[q] = from_left(vert, halo_bits(h1, H) << 16));
+                        } else {
+                            vna = S::hi(vert);
+                        }
                         f[q] = bilerp<mix_interp<S>>(oa, na, va, vna, W, n - 1);
                     }
                 }
@@ -1224,15 +1249,24 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
                     // lane 63 the halo
                     constexpr int H = M::hidx(q);
                     T nbv;
-                    if constexpr (d.cx < 0) nbv = S::lo(from_right(own, halo_bits(h0, H)));
-                    else nbv = S::lo(own);
+                    if constexpr (d.cx < 0) {
+                        if constexpr (d.cy > 0) nbv = S::lo(SY[q] = from_right(own, halo_bits(h0, H)));
+                        else if constexpr (d.cy < 0) nbv = S::lo(SX[q]);
+                        else nbv = S::lo(from_right(own, halo_bits(h0, H)));
+                    } else {
+                        nbv = S::lo(own);
+                    }
                     if constexpr (d.cy == 0) {
                         if constexpr (UNIT && n == 1) f[q] = nbv;
                         else f[q] = lerp<mix_interp<S>>(ob, nbv, W.a[n - 1]);
                     } else {
                         T vnb;
-                        if constexpr (d.cx < 0) vnb = S::lo(from_right(vert, halo_bits(d.cy > 0 ? hm : h1, H)));
-                        else vnb = S::lo(vert);
+                        if constexpr (d.cx < 0) {
+                            if constexpr (d.cy > 0) vnb = S::lo(SX[q]);
+                            else vnb = S::lo(SY[q] = from_right(vert, halo_bits(h1, H)));
+                        } else {
+                            vnb = S::lo(vert);
+                        }
                         f[q] = bilerp<mix_interp<S>>(ob, nbv, vb, vnb, W, n - 1);
                     }
                 }
@@ -1262,11 +1296,11 @@ __global__ __launch_bounds__(256, 2) void march_pair_kernel(StepArgs A) {
             h1 = h2;
         };
         for (int y = ya; y < yb; y += 3) {
-            row(y, B0, B1, B2);
+            row(y, B0, B1, B2, T0, T1, T2);
             if (y + 1 >= yb) break;
-            row(y + 1, B1, B2, B0);
+            row(y + 1, B1, B2, B0, T1, T2, T0);
             if (y + 2 >= yb) break;
-            row(y + 2, B2, B0, B1);
+            row(y + 2, B2, B0, B1, T2, T0, T1);
         }
     }
 
