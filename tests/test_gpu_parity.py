@@ -631,7 +631,8 @@ def test_paired_form_is_bitwise_equal_to_tile_form(storage, shape, cfl, forced):
         return host(lat.populations())
 
     ref = run("tile", 4)
-    for param in (0, 1, 3, 16, 500):
+    # segment lengths of every remainder mod 3 (the row loop is unrolled three times)
+    for param in (0, 1, 2, 3, 4, 16, 500):
         assert np.array_equal(run("march_pairs", param), ref), param
 
 
