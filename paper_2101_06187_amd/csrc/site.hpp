@@ -172,11 +172,12 @@ struct StBF16S {
 // for c_x, c_y both non-zero (|v_x| = |v_y|) the bilinear weights are
 // (1 - a)^2 (own node), a (1 - a) (each edge neighbour), a^2 (diagonal).
 // ---------------------------------------------------------------------------
-// Interpolation formulas.  MIX (16-bit storage): every node value is an
-// operand of a fused multiply-add, which then takes the 16-bit value as it is
-// (v_fma_mix_f32) instead of after a conversion and an addition or
-// subtraction.  Otherwise (FP32, FP64 storage) the sums of node values are
-// formed first.  Every kernel form uses the same formula for a storage type.
+// Interpolation formulas.  MIX (16-bit storage): the node values enter fused
+// multiply-adds, which take a 16-bit operand as it is (v_fma_mix_f32), rather
+// than sums or differences, which need each value converted first (only the
+// own node of the bilinear sum enters a product).  Otherwise (FP32, FP64
+// storage) the sums of node values are formed first.  Every kernel form uses
+// the same formula for a storage type, so the forms agree bit for bit.
 template <class S>
 constexpr bool mix_interp = sizeof(typename S::raw) == 2;
 
