@@ -610,8 +610,8 @@ def test_ensemble_matches_oracle(kind):
                                               ((126, 2), 1.0, False), ((248, 12), 0.9, True),
                                               ((250, 6), 1.0, True)])
 def test_paired_form_is_bitwise_equal_to_tile_form(storage, shape, cfl, forced):
-    """The paired marching form (two columns per lane, 124-column strips) on
-    ragged lattices -- the last strip 2 to 124 columns wide, a single strip
+    """The paired marching form (two columns per lane, 128-column strips) on
+    ragged lattices -- the last strip 2 to 126 columns wide, a single strip
     narrower than the wavefront's lanes, lattices of 2 and 4 columns or of 2
     rows, one or two whole strips -- equals the tile form bit for bit
     over 5 steps, for several segment lengths."""
