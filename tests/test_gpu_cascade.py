@@ -57,8 +57,13 @@ def _slope(y, lo, hi):
     return float(np.polyfit(np.log(k), np.log(y[lo:hi + 1]), 1)[0])
 
 
-def test_inertial_range_slope_on_the_paper_configuration():
-    speed, shell_sum, avg, n_f = _run(1024, 1.3e-3, 8000)
+@pytest.fixture(scope="module")
+def paper_run():
+    return _run(1024, 1.3e-3, 8000)
+
+
+def test_inertial_range_slope_on_the_paper_configuration(paper_run):
+    speed, shell_sum, avg, n_f = paper_run
     # the inertial range 0 < k < k_f: shells 4 .. 38 (shell 39 holds driven modes)
     s_avg, s_sum = _slope(avg, 4, n_f - 1), _slope(shell_sum, 4, n_f - 1)
     say("filtered speed", speed, "slope of the angular average", s_avg, "of the shell sum", s_sum)
@@ -78,3 +83,20 @@ def test_undriven_shells_are_fed_quadratically():
     say("filtered speeds", s1, s2, "ratio", s2 / s1)
     assert 3.6 <= s2 / s1 <= 4.4
     assert abs(_slope(a1, 4, n_f - 1) - _slope(a2, 4, n_f - 1)) <= 0.1
+
+
+def test_finer_lattices_of_the_same_volume_conform_better(paper_run):
+    """Sec. V's constant-volume series (N alpha = 40.96 with N = 256, 512,
+    1024, the same driven band from k_f = 6): the inertial-range slope of the
+    angular average comes closer to -5/3 as the lattice is refined.  The
+    amplitudes keep each lattice stable (the slope does not depend on them,
+    see the quadratic-feeding test)."""
+    slopes = {}
+    for n, amplitude in ((256, 1e-2), (512, 4e-3)):
+        _, _, avg, n_f = _run(n, amplitude, 8000)
+        slopes[n] = _slope(avg, 4, n_f - 1)
+    _, _, avg, n_f = paper_run
+    slopes[1024] = _slope(avg, 4, n_f - 1)
+    say("slopes of the angular average by N", slopes)
+    dev = {n: abs(s + 5.0 / 3.0) for n, s in slopes.items()}
+    assert dev[1024] < dev[512] < dev[256]
