@@ -68,6 +68,29 @@ def test_longest_side_one_step(shape):
         lat.close()
 
 
+@pytest.mark.parametrize("storage", ["F16S", "BF16S"])
+@pytest.mark.parametrize("shape", [(65536, 2), (2, 65536), (65536, 3)])
+def test_longest_side_paired_form(storage, shape):
+    """The paired 16-bit form on the largest side the ABI accepts (512
+    strips of 128 columns, or one strip of 2 columns over 65536 rows), three
+    steps from random populations, bit for bit equal to the tile form; forced
+    where the short side leaves a mode below its Nyquist wave number."""
+    nx, ny = shape
+    F0 = workloads.random_populations(SPH.v, ny, nx, seed=nx + 3 * ny, spread=0.05)
+    fr = rl.Forcing(3e-3, 1.0, 1.2, 7) if min(nx, ny) >= 3 else None
+    out = []
+    for kind, param in (("tile", 2), ("march_pairs", 0)):
+        lat = rl.Lattice(nx, ny, 0.7, storage=storage, forcing=fr)
+        lat.set_kernel(kind, param)
+        lat.set_populations(dev(oracle_to_lib(F0)))
+        lat.step(3)
+        assert lat.check() == rl.OK
+        out.append(host(lat.populations()))
+        lat.close()
+    say("longest side, paired", storage, shape)
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("shape,forced", [((65536, 3), False), ((130, 3), True), ((70, 4), False),
                                           ((2, 4099), False), ((3, 67), True)])
 def test_two_step_form_narrow_lattices(shape, forced):
