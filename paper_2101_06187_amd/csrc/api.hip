@@ -835,20 +835,16 @@ int rlbm_shell_modes(int32_t nx, int32_t ny, int32_t nbins, int64_t* h_counts) {
     const long long kx_lo = -(long long)(nx / 2), kx_hi = (long long)((nx - 1) / 2);
     const long long ky_lo = -(long long)(ny / 2), ky_hi = (long long)((ny - 1) / 2);
     const long long row = kx_hi - kx_lo + 1;
-    auto isqrt = [](long long m) {              // floor(sqrt(m)), m >= 0
-        long long r = (long long)std::sqrt((double)m);
-        while (r * r > m) --r;
-        while ((r + 1) * (r + 1) <= m) ++r;
-        return r;
-    };
     for (long long ky = ky_lo; ky <= ky_hi; ++ky) {
         // round(|k|) <= b  <=>  4 |k|^2 < (2b + 1)^2  <=>  kx^2 <= b^2 + b - ky^2
-        // (|k|^2 is an integer, so no |k| falls on a shell boundary)
-        long long prev = 0;
-        for (long long b = 0; b < nbins && prev < row; ++b) {
+        // (|k|^2 is an integer, so no |k| falls on a shell boundary).  Shells
+        // below |ky| - 1 hold none of this row; r = floor(sqrt(b^2 + b - ky^2))
+        // grows with b and is advanced, not recomputed.
+        long long prev = 0, r = 0;
+        for (long long b = std::max(0LL, std::llabs(ky) - 1); b < nbins && prev < row; ++b) {
             const long long m = b * b + b - ky * ky;
             if (m < 0) continue;
-            const long long r = isqrt(m);
+            while ((r + 1) * (r + 1) <= m) ++r;
             const long long c = std::max(0LL, std::min(r, kx_hi) - std::max(-r, kx_lo) + 1);
             h_counts[b] += c - prev;
             prev = c;
